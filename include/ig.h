@@ -1,0 +1,216 @@
+/*
+ * ig.h -- C ABI of libintergrams.so: the Intergrams per-pass scan on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Curtin, Lu, Raff, Ranade, "Intermediate N-Gramming: Deterministic
+ * and Fast N-Grams For Large N and Large Datasets" (arXiv 2511.14955).
+ *
+ *  - Problem statement (Section "Problem Formalization and Notation"): m
+ *    sequences; an n-gram is n consecutive symbols of one sequence (no gram
+ *    crosses a sequence boundary); its frequency is Eq. 1 (occurrences) or
+ *    Eq. 2 (number of sequences containing it; the paper's focus).
+ *  - A pass (Algorithm 3): count the n-grams whose (n-1)-gram prefix is in
+ *    the set retained by the previous pass and retain the k_keep most
+ *    frequent.
+ *  - Featurize (Figure 1): map sequences to Boolean rows over the retained
+ *    n-grams.
+ *
+ * Conventions for every call:
+ *  - Return IG_OK (0) or a negative IG_E* code.  The message of the last
+ *    failure is available from ig_last_error().  No C++ exception crosses the
+ *    ABI.
+ *  - Calls are synchronous: they return after the device work has finished,
+ *    except ig_serve_* which run asynchronously by design.
+ *  - The caller owns every pointer it passes.  Host buffers are read or
+ *    written before the call returns; a device pointer passed with
+ *    data_on_device = 1 must stay valid for the duration of the call.  The
+ *    library owns the device copy of the corpus, the tables and all scratch,
+ *    and ig_destroy frees them.
+ *  - One context is used by one thread at a time; the serving calls are
+ *    internally synchronized.
+ *  - IG_EDEVICE (a HIP runtime error) is sticky: every later call on the
+ *    context fails with it and the context must be destroyed.
+ */
+#ifndef IG_H
+#define IG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IG_OK          0
+#define IG_EINVAL     (-1)  /* bad argument: n = 0, n*b > 128, k_keep = 0, bad offsets, bad config */
+#define IG_ESTATE     (-2)  /* call out of order: pass n after a pass other than n-1, topk before a pass */
+#define IG_ENOMEM     (-3)  /* device allocation failed or the HBM budget would be exceeded */
+#define IG_ETRUNC     (-4)  /* caller buffer too small; the *_out argument holds the size needed */
+#define IG_EOVERFLOW  (-5)  /* 32-bit counts requested but a count could reach 2^32 */
+#define IG_EDEVICE    (-6)  /* HIP runtime error (sticky) */
+#define IG_EBUSY      (-7)  /* serving: queue full, or no serving loop running */
+
+typedef struct ig_ctx ig_ctx;
+
+/* An n-gram key: the n symbols packed most significant first into an
+ * n*b-bit integer, right-aligned (hi holds bits 64..127).  Numeric order of
+ * keys equals lexicographic order of the symbol strings. */
+typedef struct { uint64_t lo, hi; } ig_key;
+
+/* Frequency (problem statement, Eq. 1 and Eq. 2). */
+typedef enum {
+  IG_FREQ_DOC = 0,   /* Eq. 2: number of sequences containing the gram (default) */
+  IG_FREQ_OCC = 1    /* Eq. 1: number of occurrences */
+} ig_freq;
+
+typedef struct {
+  uint32_t symbol_bits;  /* 8: bytes / text; 2: DNA packed A=0 C=1 G=2 T=3 */
+  ig_freq  freq;         /* counting rule */
+  uint32_t count_bits;   /* 32 or 64: width callers need; 32 is refused with IG_EOVERFLOW
+                            when W_n >= 2^32 under IG_FREQ_OCC (Eq. 2 counts are <= m) */
+  int      device;       /* HIP device ordinal */
+  void    *stream;       /* hipStream_t to run on; NULL: the library creates one */
+  uint64_t hbm_budget;   /* bytes of device memory this context may hold; 0 = no limit */
+  uint32_t flags;        /* IG_FLAG_* */
+} ig_config;
+
+#define IG_FLAG_NO_GRAPH      1u  /* launch pass kernels directly instead of a captured hipGraph */
+#define IG_FLAG_PER_FILE      2u  /* one scan launch per file (comparison form) instead of one
+                                     persistent launch over the whole work queue */
+#define IG_FLAG_NO_AUTOTUNE   4u  /* use the built-in launch parameters */
+
+/* Fill *cfg with defaults: bytes, Eq. 2, 64-bit counts, device 0, own stream, no budget. */
+void ig_config_default(ig_config *cfg);
+
+/* Create a context on cfg->device.  On failure *out is NULL. */
+int  ig_create(const ig_config *cfg, ig_ctx **out);
+void ig_destroy(ig_ctx *ctx);
+
+/* Load m sequences, replacing any previous corpus and resetting the pass chain.
+ *  data:        symbol stream; symbol i occupies bits [i*b, i*b+b) of the stream,
+ *               most significant first within each byte (bytes when b = 8).
+ *  data_bytes:  size of data; must cover sym_offsets[m] symbols.
+ *  sym_offsets: m+1 non-decreasing symbol offsets, sym_offsets[0] = 0; sequence i is
+ *               symbols [sym_offsets[i], sym_offsets[i+1]).  Always a host array.
+ *  data_on_device: 0: data is a host pointer; 1: a device pointer on ctx's device.
+ * Errors: IG_EINVAL (offsets), IG_ENOMEM (budget / allocation), IG_EDEVICE. */
+int  ig_load_batch(ig_ctx *ctx, const void *data, uint64_t data_bytes,
+                   const uint64_t *sym_offsets, uint64_t m, int data_on_device);
+
+/* One pass (Algorithm 3): count every n-gram of the loaded sequences whose
+ * (n-1)-gram prefix is in the table retained by the previous pass (no filter
+ * when n = 1 or when no pass has run since the last load), then retain the
+ * first min(k_keep, D) of the D counted grams in the order (count desc, key asc).
+ * Errors: IG_EINVAL (n = 0, n*b > 128, k_keep = 0), IG_ESTATE (previous pass
+ * was not n-1 and the chain is not fresh, or nothing loaded), IG_EOVERFLOW,
+ * IG_ENOMEM, IG_EDEVICE.  On error the previous table is kept. */
+int  ig_pass(ig_ctx *ctx, uint32_t n, uint64_t k_keep);
+
+/* Undo the last pass: the table retained before it becomes current again
+ * (one level; the state right after ig_load_batch counts as a level), so the
+ * last pass can be run again.  Device-side pointer swap, no copy.
+ * IG_ESTATE if there is nothing to undo. */
+int  ig_rewind(ig_ctx *ctx);
+
+/* Copy the first min(k, kept) entries of the retained table (host buffers of k
+ * entries; counts may be NULL).  *k_out = number copied.  IG_ESTATE before a pass. */
+int  ig_topk(ig_ctx *ctx, uint64_t k, ig_key *keys, uint64_t *counts, uint64_t *k_out);
+
+/* Gram length n and size of the retained table (0, 0 before any pass). */
+int  ig_table_info(const ig_ctx *ctx, uint32_t *n, uint64_t *kept);
+
+/* Boolean feature rows (Figure 1) of m new sequences against the retained table:
+ * row i lists, ascending, the 0-based ranks of retained grams occurring in
+ * sequence i.  data / sym_offsets as in ig_load_batch (data is a host pointer).
+ *  indptr:  host array of m+1 entries (row i = indices[indptr[i] .. indptr[i+1])).
+ *  indices: host array of cap entries.
+ *  *nnz_out: total entries.  IG_ETRUNC if nnz > cap (indptr is still filled).
+ * The loaded corpus and the pass chain are not changed. */
+int  ig_featurize(ig_ctx *ctx, const void *data, uint64_t data_bytes,
+                  const uint64_t *sym_offsets, uint64_t m,
+                  uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out);
+
+/* Per-pass measurements of the last ig_pass: device time of the whole pass and of
+ * the scan kernel (milliseconds, hipEvent-timed on the context's stream), windows
+ * scanned, distinct grams counted, and the scan kernel's average duration. */
+typedef struct {
+  double   pass_ms;
+  double   scan_ms;
+  double   select_ms;
+  uint64_t windows;
+  uint64_t distinct;
+  uint64_t input_bytes;
+  uint32_t replays;      /* times the pass was re-run after growing a table */
+  uint32_t chunk_syms;   /* launch parameters in use */
+  uint32_t block;
+  uint32_t grid;
+} ig_pass_stats;
+int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
+
+const char *ig_last_error(const ig_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Serving (continuous batching of featurize / count requests).
+ *
+ * A background thread admits submitted requests while the device memory they
+ * need (input, output and scratch) fits max_inflight_bytes, packs every
+ * admitted request into the next launch on one of n_streams streams, and
+ * completes them as launches finish.  Requests that arrive while others run
+ * are admitted as soon as memory frees; launches on different streams
+ * overlap.  The table used is the context's retained table at
+ * ig_serve_start; the context must not run passes while serving.
+ *
+ * kind IG_REQ_FEATURIZE: the result is the Boolean row of one sequence
+ *   (int32 ranks, ascending), as ig_featurize.
+ * kind IG_REQ_COUNT: the result is, over the request's sequences, the number
+ *   of sequences containing each retained gram, as (rank, count) pairs with
+ *   rank ascending and count > 0 (Eq. 2 restricted to the table).
+ * --------------------------------------------------------------------------- */
+#define IG_REQ_FEATURIZE 0
+#define IG_REQ_COUNT     1
+
+typedef struct {
+  uint64_t max_inflight_bytes;  /* HBM admission budget for in-flight requests */
+  uint32_t n_streams;           /* concurrent launches (1..8) */
+  uint32_t max_batch;           /* most requests packed into one launch */
+  uint64_t queue_capacity;      /* most submitted, not yet completed requests */
+} ig_serve_config;
+
+int ig_serve_start(ig_ctx *ctx, const ig_serve_config *scfg);
+/* Submit one request (a copy of data is taken before returning).
+ *  sym_offsets: m+1 offsets of the request's sequences (m = 1 for featurize).
+ *  tag: caller id returned with the result.  t_arrival: caller clock (seconds),
+ *  returned with the result.  IG_EBUSY when the queue is full. */
+int ig_submit(ig_ctx *ctx, int kind, const void *data, uint64_t data_bytes,
+              const uint64_t *sym_offsets, uint64_t m, uint64_t tag, double t_arrival);
+
+typedef struct {
+  uint64_t tag;
+  int      kind;
+  int      status;         /* IG_OK or an error for this request */
+  double   t_arrival;      /* as submitted */
+  double   t_done;         /* library clock (seconds, same base as ig_serve_now) when the result was on the host */
+  uint64_t n;              /* entries in the result */
+} ig_result;
+
+/* Take up to max completed results (oldest first).  For each, up to cap entries are
+ * copied to cols[] (and counts[] for COUNT requests, may be NULL otherwise) at
+ * offset out_off[i]; out_off has max+1 entries.  *n_out = results taken. */
+int ig_poll(ig_ctx *ctx, ig_result *res, uint64_t max, int32_t *cols, uint64_t *counts,
+            uint64_t cap, uint64_t *out_off, uint64_t *n_out);
+/* Library clock in seconds (CLOCK_MONOTONIC). */
+double ig_serve_now(void);
+/* Stop admitting, drain in-flight work, join the serving thread. */
+int ig_serve_stop(ig_ctx *ctx);
+
+typedef struct {
+  uint64_t submitted, completed, launches, rejected;
+  uint64_t peak_inflight_bytes;
+  uint64_t bytes_in;
+} ig_serve_stats;
+int ig_serve_get_stats(ig_ctx *ctx, ig_serve_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IG_H */

@@ -1,0 +1,223 @@
+"""Python binding of libintergrams.so (the Intergrams per-pass scan on MI355X).
+
+Argument marshalling only: every step of a pass, of featurize and of serving
+runs in the library's HIP kernels.  There is no CPU fallback: if the shared
+library is missing or fails to load, importing the binding's entry points
+raises.
+
+PyTorch is optional here; when given, torch CUDA tensors are passed as device
+pointers and torch's current stream can be handed to the library.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libintergrams.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "ig.h")
+
+IG_OK, IG_EINVAL, IG_ESTATE, IG_ENOMEM, IG_ETRUNC, IG_EOVERFLOW, IG_EDEVICE, IG_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
+FREQ_DOC, FREQ_OCC = 0, 1
+FLAG_NO_GRAPH, FLAG_PER_FILE, FLAG_NO_AUTOTUNE = 1, 2, 4
+REQ_FEATURIZE, REQ_COUNT = 0, 1
+
+_ERRNAMES = {IG_EINVAL: "IG_EINVAL", IG_ESTATE: "IG_ESTATE", IG_ENOMEM: "IG_ENOMEM", IG_ETRUNC: "IG_ETRUNC",
+             IG_EOVERFLOW: "IG_EOVERFLOW", IG_EDEVICE: "IG_EDEVICE", IG_EBUSY: "IG_EBUSY"}
+
+
+class IGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class ig_key(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
+
+
+class ig_config(ctypes.Structure):
+    _fields_ = [("symbol_bits", ctypes.c_uint32), ("freq", ctypes.c_int), ("count_bits", ctypes.c_uint32),
+                ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("hbm_budget", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class ig_pass_stats(ctypes.Structure):
+    _fields_ = [("pass_ms", ctypes.c_double), ("scan_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
+                ("windows", ctypes.c_uint64), ("distinct", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
+                ("replays", ctypes.c_uint32), ("chunk_syms", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32)]
+
+
+class ig_serve_config(ctypes.Structure):
+    _fields_ = [("max_inflight_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("queue_capacity", ctypes.c_uint64)]
+
+
+class ig_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("kind", ctypes.c_int), ("status", ctypes.c_int),
+                ("t_arrival", ctypes.c_double), ("t_done", ctypes.c_double), ("n", ctypes.c_uint64)]
+
+
+class ig_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64), ("bytes_in", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def header_functions():
+    """Names of the functions that include/ig.h declares."""
+    with open(HEADER) as fh:
+        text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(ig_[a-z_]+)\s*\(", text)))
+
+
+def load_library(path=LIB_PATH):
+    """Load libintergrams.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libintergrams.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    vp, u64, u32, i32, dbl = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    lib.ig_config_default.argtypes = [P(ig_config)]
+    lib.ig_config_default.restype = None
+    lib.ig_create.argtypes = [P(ig_config), P(vp)]
+    lib.ig_destroy.argtypes = [vp]
+    lib.ig_destroy.restype = None
+    lib.ig_load_batch.argtypes = [vp, vp, u64, P(u64), u64, i32]
+    lib.ig_pass.argtypes = [vp, u32, u64]
+    lib.ig_rewind.argtypes = [vp]
+    lib.ig_topk.argtypes = [vp, u64, vp, vp, P(u64)]
+    lib.ig_table_info.argtypes = [vp, P(u32), P(u64)]
+    lib.ig_featurize.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
+    lib.ig_last_pass_stats.argtypes = [vp, P(ig_pass_stats)]
+    lib.ig_last_error.argtypes = [vp]
+    lib.ig_last_error.restype = ctypes.c_char_p
+    if hasattr(lib, "ig_serve_start"):
+        lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
+        lib.ig_submit.argtypes = [vp, i32, vp, u64, P(u64), u64, u64, dbl]
+        lib.ig_poll.argtypes = [vp, P(ig_result), u64, vp, vp, u64, P(u64), P(u64)]
+        lib.ig_serve_now.argtypes = []
+        lib.ig_serve_now.restype = dbl
+        lib.ig_serve_stop.argtypes = [vp]
+        lib.ig_serve_get_stats.argtypes = [vp, P(ig_serve_stats)]
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _u64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+def _as_host(corpus_or_data, offsets=None):
+    if offsets is None:
+        data, offsets = corpus_or_data.data, corpus_or_data.offsets
+    else:
+        data = corpus_or_data
+    return data, np.ascontiguousarray(offsets, np.uint64)
+
+
+class Intergrams:
+    """One library context on one GPU."""
+
+    def __init__(self, symbol_bits=8, freq=FREQ_DOC, count_bits=64, device=0, stream=None, hbm_budget=0, flags=0):
+        self._lib = load_library()
+        cfg = ig_config()
+        self._lib.ig_config_default(ctypes.byref(cfg))
+        cfg.symbol_bits, cfg.freq, cfg.count_bits, cfg.device = symbol_bits, freq, count_bits, device
+        cfg.stream = stream if stream is None or isinstance(stream, int) else int(stream.cuda_stream)
+        cfg.hbm_budget, cfg.flags = hbm_budget, flags
+        h = ctypes.c_void_p()
+        rc = self._lib.ig_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc:
+            raise IGError(rc, "ig_create failed")
+        self._h = h
+        self.symbol_bits = symbol_bits
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ig_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, rc):
+        if rc:
+            raise IGError(rc, self._lib.ig_last_error(self._h).decode(errors="replace"))
+        return rc
+
+    def load(self, corpus_or_data, offsets=None):
+        """Load a gen.Corpus, or (data, offsets); data may be a numpy array or a torch CUDA tensor."""
+        data, offs = _as_host(corpus_or_data, offsets)
+        if hasattr(data, "is_cuda") and data.is_cuda:
+            ptr, nbytes, on_dev = data.data_ptr(), data.numel() * data.element_size(), 1
+        else:
+            data = np.ascontiguousarray(data, np.uint8)
+            ptr, nbytes, on_dev = data.ctypes.data, data.nbytes, 0
+        self._check(self._lib.ig_load_batch(self._h, ptr, nbytes, _u64p(offs), len(offs) - 1, on_dev))
+
+    def pass_(self, n, k_keep):
+        return self._check(self._lib.ig_pass(self._h, n, k_keep))
+
+    def rewind(self):
+        """Make the table retained before the last pass current again."""
+        return self._check(self._lib.ig_rewind(self._h))
+
+    def try_pass(self, n, k_keep):
+        """ig_pass's return code (no exception)."""
+        return int(self._lib.ig_pass(self._h, n, k_keep))
+
+    def table_info(self):
+        n, k = ctypes.c_uint32(), ctypes.c_uint64()
+        self._check(self._lib.ig_table_info(self._h, ctypes.byref(n), ctypes.byref(k)))
+        return n.value, k.value
+
+    def topk(self, k=None):
+        """(keys (k, 2) uint64 lo/hi, counts uint64) of the retained table, in order."""
+        if k is None:
+            k = self.table_info()[1]
+        keys = np.zeros((max(k, 1), 2), np.uint64)
+        counts = np.zeros(max(k, 1), np.uint64)
+        kout = ctypes.c_uint64()
+        self._check(self._lib.ig_topk(self._h, k, keys.ctypes.data, counts.ctypes.data, ctypes.byref(kout)))
+        return keys[:kout.value], counts[:kout.value]
+
+    def table(self):
+        keys, counts = self.topk()
+        return [(int(lo) | (int(hi) << 64), int(c)) for (lo, hi), c in zip(keys, counts)]
+
+    def featurize(self, corpus_or_data, offsets=None):
+        data, offs = _as_host(corpus_or_data, offsets)
+        data = np.ascontiguousarray(data, np.uint8)
+        m = len(offs) - 1
+        indptr = np.zeros(m + 1, np.uint64)
+        nnz = ctypes.c_uint64()
+        cap = 1 << 16
+        while True:
+            ind = np.zeros(max(cap, 1), np.int32)
+            rc = self._lib.ig_featurize(self._h, data.ctypes.data, data.nbytes, _u64p(offs), m, _u64p(indptr),
+                                        ind.ctypes.data, cap, ctypes.byref(nnz))
+            if rc == IG_ETRUNC:
+                cap = int(nnz.value)
+                continue
+            self._check(rc)
+            return indptr, ind[:nnz.value]
+
+    def last_stats(self):
+        st = ig_pass_stats()
+        self._check(self._lib.ig_last_pass_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ig_pass_stats._fields_}

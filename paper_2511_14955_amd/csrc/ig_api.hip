@@ -1,0 +1,573 @@
+// C ABI of libintergrams.so: contexts, corpus load, passes, table access, featurize.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "ig_internal.h"
+
+namespace ig {
+
+int set_error(ig_ctx *c, int code, const char *fmt, ...) {
+  if (!c) return code;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  c->err = buf;
+  if (code == IG_EDEVICE) c->sticky = 1;
+  return code;
+}
+
+int check_hip(ig_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return 0;
+  set_error(c, IG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return 1;
+}
+
+int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.p && b.bytes >= bytes) return 0;
+  size_t want = bytes + bytes / 8;
+  if (b.p) {
+    // the stream may still use the old buffer
+    if (check_hip(c, hipStreamSynchronize(c->stream), "sync before realloc")) return IG_EDEVICE;
+    (void)hipFree(b.p);
+    c->held_bytes -= b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  if (c->cfg.hbm_budget && c->held_bytes + want > c->cfg.hbm_budget) {
+    want = bytes;
+    if (c->held_bytes + want > c->cfg.hbm_budget) {
+      set_error(c, IG_ENOMEM, "HBM budget exceeded: holding %llu, need %llu more, budget %llu",
+                (unsigned long long)c->held_bytes, (unsigned long long)want, (unsigned long long)c->cfg.hbm_budget);
+      return IG_ENOMEM;
+    }
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(c, IG_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)want, hipGetErrorString(e));
+    return IG_ENOMEM;
+  }
+  b.p = p;
+  b.bytes = want;
+  c->held_bytes += want;
+  return 0;
+}
+
+void dev_release(ig_ctx *c, DevBuf &b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->held_bytes -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// symbol histogram over [0, total_syms) of the stream
+__global__ void k_sym_hist(const uint8_t *data, uint64_t total_syms, uint32_t bits, unsigned long long *hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  if (bits == 8) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total_syms / 16; i += stride) {
+      const uint4 v = reinterpret_cast<const uint4 *>(data)[i];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      for (int j = 0; j < 4; j++)
+        for (int k = 0; k < 4; k++) atomicAdd(&h[(w[j] >> (8 * k)) & 255], 1u);
+    }
+    for (uint64_t i = (total_syms / 16) * 16 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < total_syms; i += stride)
+      atomicAdd(&h[data[i]], 1u);
+  } else {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < total_syms; g += stride)
+      atomicAdd(&h[(data[g >> 2] >> (6 - 2 * (g & 3))) & 3], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
+}
+
+static int count_bits_for(uint64_t maxv) {
+  int b = 1;
+  while (b < 64 && (maxv >> b)) b++;
+  return b;
+}
+
+static uint64_t windows_of(const ig_ctx *c, uint32_t n) {
+  uint64_t w = 0;
+  for (uint64_t i = 0; i < c->m; i++) {
+    const uint64_t L = c->h_offs[i + 1] - c->h_offs[i];
+    if (L >= n) w += L - n + 1;
+  }
+  return w;
+}
+
+static int upload_chunks(ig_ctx *c) {
+  std::vector<Chunk> ch;
+  c->file_chunk0.assign(c->m + 1, 0);
+  const uint64_t CH = c->lc.chunk_syms;
+  for (uint64_t f = 0; f < c->m; f++) {
+    c->file_chunk0[f] = (uint32_t)ch.size();
+    const uint64_t a = c->h_offs[f], L = c->h_offs[f + 1] - a;
+    for (uint64_t s = 0; s < L; s += CH) {
+      Chunk k{};
+      k.s0 = a + s;
+      k.file = (uint32_t)f;
+      k.nsym = (uint32_t)std::min<uint64_t>(CH, L - s);
+      k.multi = L > CH ? 1u : 0u;
+      ch.push_back(k);
+    }
+  }
+  c->file_chunk0[c->m] = (uint32_t)ch.size();
+  c->nchunks = ch.size();
+  std::vector<Chunk> lpt(ch);
+  std::stable_sort(lpt.begin(), lpt.end(), [](const Chunk &x, const Chunk &y) { return x.nsym > y.nsym; });
+  const size_t bytes = std::max<size_t>(1, ch.size()) * sizeof(Chunk);
+  if (dev_reserve(c, c->chunks_file, bytes) || dev_reserve(c, c->chunks_lpt, bytes)) return IG_ENOMEM;
+  if (!ch.empty()) {
+    if (check_hip(c, hipMemcpyAsync(c->chunks_file.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, c->stream),
+                  "chunk upload") ||
+        check_hip(c, hipMemcpyAsync(c->chunks_lpt.p, lpt.data(), lpt.size() * sizeof(Chunk), hipMemcpyHostToDevice, c->stream),
+                  "chunk upload") ||
+        check_hip(c, hipStreamSynchronize(c->stream), "chunk upload sync"))
+      return IG_EDEVICE;
+  }
+  return IG_OK;
+}
+
+}  // namespace ig
+
+using namespace ig;
+
+extern "C" {
+
+void ig_config_default(ig_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->symbol_bits = 8;
+  cfg->freq = IG_FREQ_DOC;
+  cfg->count_bits = 64;
+  cfg->device = 0;
+  cfg->stream = nullptr;
+  cfg->hbm_budget = 0;
+  cfg->flags = 0;
+}
+
+int ig_create(const ig_config *cfg, ig_ctx **out) {
+  if (!out) return IG_EINVAL;
+  *out = nullptr;
+  if (!cfg || (cfg->symbol_bits != 8 && cfg->symbol_bits != 2) || (cfg->count_bits != 32 && cfg->count_bits != 64) ||
+      (cfg->freq != IG_FREQ_DOC && cfg->freq != IG_FREQ_OCC))
+    return IG_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
+    (void)hipGetLastError();
+    return IG_EDEVICE;
+  }
+  ig_ctx *c = new (std::nothrow) ig_ctx();
+  if (!c) return IG_ENOMEM;
+  c->cfg = *cfg;
+  if (hipSetDevice(cfg->device) != hipSuccess) { delete c; return IG_EDEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, cfg->device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
+  if (cfg->stream) {
+    c->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) { delete c; return IG_EDEVICE; }
+    c->own_stream = true;
+  }
+  for (auto &e : c->ev)
+    if (hipEventCreate(&e) != hipSuccess) { delete c; return IG_EDEVICE; }
+  if (cfg->symbol_bits == 2) c->lc.chunk_syms = 65536;
+  if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->code, 256) ||
+      dev_reserve(c, c->sym_of_code, 256)) {
+    ig_destroy(c);
+    return IG_ENOMEM;
+  }
+  *out = c;
+  return IG_OK;
+}
+
+void ig_destroy(ig_ctx *c) {
+  if (!c) return;
+  serve_teardown(c);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
+                    &c->status, &c->cnt, &c->pset, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
+                    &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
+  for (DevBuf *b : bufs) dev_release(c, *b);
+  for (TableSet &t : c->ts) {
+    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map_lo, &t.map_hi, &t.map_val, &t.filt};
+    for (DevBuf *b : tb) dev_release(c, *b);
+  }
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *ig_last_error(const ig_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int ig_load_batch(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
+                  int data_on_device) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  if (!sym_offsets || sym_offsets[0] != 0) return set_error(c, IG_EINVAL, "sym_offsets[0] must be 0");
+  if (m >= 0xFFFFFFFEull) return set_error(c, IG_EINVAL, "too many sequences");
+  for (uint64_t i = 0; i < m; i++)
+    if (sym_offsets[i + 1] < sym_offsets[i]) return set_error(c, IG_EINVAL, "sym_offsets not monotone at %llu", (unsigned long long)i);
+  const uint32_t b = c->cfg.symbol_bits;
+  const uint64_t total = sym_offsets[m];
+  const uint64_t need = (total * b + 7) / 8;
+  if (data_bytes < need) return set_error(c, IG_EINVAL, "data_bytes %llu < %llu needed", (unsigned long long)data_bytes, (unsigned long long)need);
+  if (need && !data) return set_error(c, IG_EINVAL, "null data");
+  if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
+  c->loaded = false;
+  c->fresh = true;
+  c->can_rewind = false;
+  c->n_prev = 0;
+  c->kept = 0;
+  const uint64_t alloc = ((need + 15) & ~15ull) + 64;
+  if (dev_reserve(c, c->data, alloc) || dev_reserve(c, c->offs, (m + 1) * 8)) return IG_ENOMEM;
+  hipStream_t s = c->stream;
+  if (need) {
+    if (check_hip(c, hipMemcpyAsync(c->data.p, data, need, data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s),
+                  "corpus copy"))
+      return IG_EDEVICE;
+  }
+  // zero the tail so that 16-byte staging past the last symbol reads zeros
+  if (check_hip(c, hipMemsetAsync(reinterpret_cast<uint8_t *>(c->data.p) + need, 0, alloc - need, s), "tail zero"))
+    return IG_EDEVICE;
+  c->h_offs.assign(sym_offsets, sym_offsets + m + 1);
+  c->m = m;
+  c->total_syms = total;
+  c->data_bytes = need;
+  if (check_hip(c, hipMemcpyAsync(c->offs.p, sym_offsets, (m + 1) * 8, hipMemcpyHostToDevice, s), "offsets copy"))
+    return IG_EDEVICE;
+  // alphabet actually present (the candidate space uses the compacted alphabet)
+  if (dev_reserve(c, c->hist, 512 * 8)) return IG_ENOMEM;
+  if (launch_fill_u64(reinterpret_cast<uint64_t *>(c->hist.p), 256, 0, s) != hipSuccess) return set_error(c, IG_EDEVICE, "fill");
+  if (total) {
+    uint64_t g = (total / 16 + 255) / 256;
+    g = std::max<uint64_t>(1, std::min<uint64_t>(g, (uint64_t)c->n_cu * 8));
+    hipLaunchKernelGGL(k_sym_hist, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint8_t *>(c->data.p), total, b,
+                       reinterpret_cast<unsigned long long *>(c->hist.p));
+  }
+  unsigned long long hh[256];
+  if (check_hip(c, hipMemcpyAsync(hh, c->hist.p, sizeof hh, hipMemcpyDeviceToHost, s), "hist copy") ||
+      check_hip(c, hipStreamSynchronize(s), "hist sync"))
+    return IG_EDEVICE;
+  uint32_t sigma = 0;
+  std::memset(c->h_code, 0, 256);
+  std::memset(c->h_sym_of_code, 0, 256);
+  for (int v = 0; v < (1 << b); v++)
+    if (hh[v]) {
+      c->h_code[v] = (uint8_t)sigma;
+      c->h_sym_of_code[sigma] = (uint8_t)v;
+      sigma++;
+    }
+  c->sigma = sigma ? sigma : 1;
+  if (check_hip(c, hipMemcpyAsync(c->code.p, c->h_code, 256, hipMemcpyHostToDevice, s), "code copy") ||
+      check_hip(c, hipMemcpyAsync(c->sym_of_code.p, c->h_sym_of_code, 256, hipMemcpyHostToDevice, s), "code copy"))
+    return IG_EDEVICE;
+  int rc = upload_chunks(c);
+  if (rc) return rc;
+  c->loaded = true;
+  return IG_OK;
+}
+
+int ig_table_info(const ig_ctx *c, uint32_t *n, uint64_t *kept) {
+  if (!c) return IG_EINVAL;
+  if (n) *n = c->fresh ? 0 : c->n_prev;
+  if (kept) *kept = c->fresh ? 0 : c->kept;
+  return IG_OK;
+}
+
+int ig_last_pass_stats(const ig_ctx *c, ig_pass_stats *st) {
+  if (!c || !st) return IG_EINVAL;
+  *st = c->last;
+  return IG_OK;
+}
+
+int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  const uint32_t b = c->cfg.symbol_bits;
+  if (n == 0 || (uint64_t)n * b > 128 || k_keep == 0) return set_error(c, IG_EINVAL, "bad n=%u or k_keep", n);
+  if (!c->loaded) return set_error(c, IG_ESTATE, "no corpus loaded");
+  const bool filtered = !(n == 1 || c->fresh);
+  if (filtered && c->n_prev != n - 1) return set_error(c, IG_ESTATE, "pass %u must follow pass %u", n, n - 1);
+  const uint64_t W = windows_of(c, n);
+  const bool occ = c->cfg.freq == IG_FREQ_OCC;
+  if (occ && c->cfg.count_bits == 32 && W >= (1ull << 32))
+    return set_error(c, IG_EOVERFLOW, "W_n = %llu windows need 64-bit counts", (unsigned long long)W);
+  if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
+  hipStream_t s = c->stream;
+  const int mode = filtered ? MODE_FILTERED : ((uint64_t)n * b <= 26 ? MODE_DENSE : MODE_SPARSE);
+  const int kw = (uint64_t)n * b > 64 ? 2 : 1;
+  const int count64 = occ && W >= 0xFFFFFFFFull ? 1 : 0;
+  const uint32_t cbits = (uint32_t)count_bits_for(occ ? std::max<uint64_t>(W, 1) : std::max<uint64_t>(c->m, 1));
+  c->last = ig_pass_stats{};
+  c->last.windows = W;
+  c->last.input_bytes = c->data_bytes;
+
+  // candidate space
+  uint64_t nc = 0;
+  if (mode == MODE_DENSE) nc = 1ull << (n * b);
+  else if (mode == MODE_FILTERED) nc = c->kept * c->sigma;
+  else {
+    if (!c->tkey_slots) {
+      uint64_t want = std::min<uint64_t>(std::max<uint64_t>(W, 1), 1ull << 26) * 2;
+      uint64_t cap = 1ull << 16;
+      while (cap < want) cap <<= 1;
+      c->tkey_slots = cap;
+    }
+    nc = c->tkey_slots;
+  }
+  if (nc >= 0xFFFFFFFFull) return set_error(c, IG_ENOMEM, "candidate space %llu too large", (unsigned long long)nc);
+
+  ScanParams p{};
+  p.data = reinterpret_cast<const uint8_t *>(c->data.p);
+  p.offs = reinterpret_cast<const uint64_t *>(c->offs.p);
+  p.n = n;
+  p.sigma = c->sigma;
+  p.code = reinterpret_cast<const uint8_t *>(c->code.p);
+  p.status = reinterpret_cast<uint32_t *>(c->status.p);
+  p.qctr = reinterpret_cast<uint32_t *>(c->qctr.p);
+  if (mode == MODE_FILTERED) {
+    const TableSet &t = c->T();
+    p.filt = reinterpret_cast<const uint32_t *>(t.filt.p);
+    p.filt_words = t.filt_words;
+    p.filt_kind = t.filt_kind;
+    p.mkey_lo = reinterpret_cast<const uint64_t *>(t.map_lo.p);
+    p.mkey_hi = reinterpret_cast<const uint64_t *>(t.map_hi.p);
+    p.mval = reinterpret_cast<const uint32_t *>(t.map_val.p);
+    p.mmask = t.map_mask;
+  }
+  p.set_cap = c->lc.set_cap;
+  p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
+  const uint32_t block = c->lc.block;
+  const uint32_t grid = (uint32_t)c->n_cu * c->lc.grid_per_cu;
+  c->last.chunk_syms = c->lc.chunk_syms;
+  c->last.block = block;
+  c->last.grid = grid;
+
+  uint32_t replays = 0;
+  float scan_ms = 0.f;
+  if (check_hip(c, hipEventRecord(c->ev[0], s), "event")) return IG_EDEVICE;
+  for (;;) {
+    if (dev_reserve(c, c->cnt, nc * (count64 ? 8 : 4))) return IG_ENOMEM;
+    p.cnt = c->cnt.p;
+    if (!occ) {
+      if (dev_reserve(c, c->pset, c->pset_slots * 8)) return IG_ENOMEM;
+      p.pset = reinterpret_cast<uint64_t *>(c->pset.p);
+      p.pmask = c->pset_slots - 1;
+    }
+    if (mode == MODE_SPARSE) {
+      if (dev_reserve(c, c->tkey_lo, c->tkey_slots * 8) || dev_reserve(c, c->tkey_hi, c->tkey_slots * 8) ||
+          dev_reserve(c, c->tstate, c->tkey_slots * 4))
+        return IG_ENOMEM;
+      p.tkey_lo = reinterpret_cast<uint64_t *>(c->tkey_lo.p);
+      p.tkey_hi = reinterpret_cast<uint64_t *>(c->tkey_hi.p);
+      p.tstate = reinterpret_cast<uint32_t *>(c->tstate.p);
+      p.tmask = c->tkey_slots - 1;
+      nc = c->tkey_slots;
+    }
+    hipError_t e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
+                           : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
+    if (e == hipSuccess && !occ) e = launch_fill_u64(p.pset, c->pset_slots, 0, s);
+    if (e == hipSuccess && mode == MODE_SPARSE) e = launch_fill_u32(p.tstate, c->tkey_slots, 0, s);
+    if (e == hipSuccess) e = launch_fill_u32(p.status, 16, 0, s);
+    if (e == hipSuccess) e = launch_fill_u32(p.qctr, 16, 0, s);
+    if (check_hip(c, e, "pass fill")) return IG_EDEVICE;
+    if (check_hip(c, hipEventRecord(c->ev[1], s), "event")) return IG_EDEVICE;
+    if (c->cfg.flags & IG_FLAG_PER_FILE) {
+      p.persistent = 0;
+      p.chunks = reinterpret_cast<const Chunk *>(c->chunks_file.p);
+      for (uint64_t f = 0; f < c->m; f++) {
+        const uint32_t c0 = c->file_chunk0[f], c1 = c->file_chunk0[f + 1];
+        if (c1 == c0) continue;
+        p.chunk_base = c0;
+        p.nchunks = c1 - c0;
+        e = launch_scan(p, b, kw, mode, occ, count64, c1 - c0, block, s);
+        if (e != hipSuccess) break;
+      }
+    } else {
+      p.persistent = 1;
+      p.chunks = reinterpret_cast<const Chunk *>(c->chunks_lpt.p);
+      p.chunk_base = 0;
+      p.nchunks = (uint32_t)c->nchunks;
+      if (c->nchunks) e = launch_scan(p, b, kw, mode, occ, count64, grid, block, s);
+    }
+    if (check_hip(c, e, "scan launch")) return IG_EDEVICE;
+    if (check_hip(c, hipEventRecord(c->ev[2], s), "event")) return IG_EDEVICE;
+    uint32_t status = 0;
+    if (check_hip(c, hipMemcpyAsync(&status, p.status, 4, hipMemcpyDeviceToHost, s), "status copy") ||
+        check_hip(c, hipStreamSynchronize(s), "scan sync"))
+      return IG_EDEVICE;
+    (void)hipEventElapsedTime(&scan_ms, c->ev[1], c->ev[2]);
+    if (!status) break;
+    if (status & ST_PSET_OVF) c->pset_slots <<= 2;
+    if (status & ST_TABLE_OVF) c->tkey_slots <<= 2;
+    if (++replays > 8) return set_error(c, IG_ENOMEM, "tables kept overflowing (status %u)", status);
+  }
+  c->last.replays = replays;
+  c->last.scan_ms = scan_ms;
+
+  // selection
+  SelectParams sp{};
+  sp.cnt = c->cnt.p;
+  sp.nc = nc;
+  sp.count64 = count64;
+  sp.mode = mode;
+  sp.bits = b;
+  sp.sigma = c->sigma;
+  sp.sym_of_code = reinterpret_cast<const uint8_t *>(c->sym_of_code.p);
+  sp.pk_lo = reinterpret_cast<const uint64_t *>(c->T().lo.p);
+  sp.pk_hi = reinterpret_cast<const uint64_t *>(c->T().hi.p);
+  sp.tk_lo = reinterpret_cast<const uint64_t *>(c->tkey_lo.p);
+  sp.tk_hi = reinterpret_cast<const uint64_t *>(c->tkey_hi.p);
+  uint64_t kept = 0;
+  if (check_hip(c, hipEventRecord(c->ev[3], s), "event")) return IG_EDEVICE;
+  int rc = run_select(c, sp, k_keep, n * b, count64 ? 64 : cbits, &kept);
+  if (rc) return rc;
+  float sel_ms = 0.f;
+  // commit: the new table (set nxt) becomes current; the old current is kept for ig_rewind
+  TableSet &nt = c->ts[c->nxt];
+  nt.kept = kept;
+  nt.n = n;
+  rc = build_table_index(c, nt);
+  if (rc) return rc;
+  {
+    const int old_prev = c->prev;
+    c->prev = c->cur;
+    c->cur = c->nxt;
+    c->nxt = old_prev;
+  }
+  c->prev_fresh = c->fresh;
+  c->can_rewind = true;
+  c->kept = kept;
+  c->n_prev = n;
+  c->fresh = false;
+  if (check_hip(c, hipEventRecord(c->ev[2], s), "event") || check_hip(c, hipStreamSynchronize(s), "pass sync"))
+    return IG_EDEVICE;
+  float total_ms = 0.f;
+  (void)hipEventElapsedTime(&total_ms, c->ev[0], c->ev[2]);
+  (void)hipEventElapsedTime(&sel_ms, c->ev[3], c->ev[2]);
+  c->last.pass_ms = total_ms;
+  c->last.select_ms = sel_ms;
+  return IG_OK;
+}
+
+int ig_rewind(ig_ctx *c) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  if (!c->can_rewind) return set_error(c, IG_ESTATE, "nothing to rewind");
+  std::swap(c->cur, c->prev);
+  c->fresh = c->prev_fresh;
+  c->n_prev = c->fresh ? 0 : c->T().n;
+  c->kept = c->fresh ? 0 : c->T().kept;
+  c->can_rewind = false;
+  return IG_OK;
+}
+
+int ig_topk(ig_ctx *c, uint64_t k, ig_key *keys, uint64_t *counts, uint64_t *k_out) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->fresh || !c->loaded) return set_error(c, IG_ESTATE, "no pass has run");
+  const uint64_t cnt = std::min(k, c->kept);
+  if (k_out) *k_out = cnt;
+  if (!cnt) return IG_OK;
+  if (!keys && !counts) return IG_OK;
+  std::vector<uint64_t> lo(cnt), hi(cnt);
+  hipStream_t s = c->stream;
+  if (keys) {
+    if (check_hip(c, hipMemcpyAsync(lo.data(), c->T().lo.p, cnt * 8, hipMemcpyDeviceToHost, s), "topk copy") ||
+        check_hip(c, hipMemcpyAsync(hi.data(), c->T().hi.p, cnt * 8, hipMemcpyDeviceToHost, s), "topk copy"))
+      return IG_EDEVICE;
+  }
+  if (counts && check_hip(c, hipMemcpyAsync(counts, c->T().cnt.p, cnt * 8, hipMemcpyDeviceToHost, s), "topk copy"))
+    return IG_EDEVICE;
+  if (check_hip(c, hipStreamSynchronize(s), "topk sync")) return IG_EDEVICE;
+  if (keys)
+    for (uint64_t i = 0; i < cnt; i++) keys[i] = ig_key{lo[i], hi[i]};
+  return IG_OK;
+}
+
+int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
+                 uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->fresh || !c->loaded) return set_error(c, IG_ESTATE, "no pass has run");
+  if (!sym_offsets || sym_offsets[0] != 0 || !indptr) return set_error(c, IG_EINVAL, "bad offsets");
+  for (uint64_t i = 0; i < m; i++)
+    if (sym_offsets[i + 1] < sym_offsets[i]) return set_error(c, IG_EINVAL, "sym_offsets not monotone");
+  const uint32_t b = c->cfg.symbol_bits;
+  const uint64_t need = (sym_offsets[m] * b + 7) / 8;
+  if (data_bytes < need || (need && !data)) return set_error(c, IG_EINVAL, "data too small");
+  hipStream_t s = c->stream;
+  const uint32_t words = (uint32_t)((c->kept + 31) / 32);
+  // chunks of the batch
+  std::vector<Chunk> ch;
+  const uint64_t CH = c->lc.chunk_syms;
+  for (uint64_t f = 0; f < m; f++) {
+    const uint64_t a = sym_offsets[f], L = sym_offsets[f + 1] - a;
+    for (uint64_t q = 0; q < L; q += CH) ch.push_back(Chunk{a + q, (uint32_t)f, (uint32_t)std::min<uint64_t>(CH, L - q), L > CH ? 1u : 0u, 0u});
+  }
+  DevBuf d_data, d_offs, d_ch, d_bm, d_nnz, d_ind, d_ptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    dev_release(c, d_data); dev_release(c, d_offs); dev_release(c, d_ch); dev_release(c, d_bm);
+    dev_release(c, d_nnz); dev_release(c, d_ind); dev_release(c, d_ptr);
+  };
+  const uint64_t alloc = ((need + 15) & ~15ull) + 64;
+  if (dev_reserve(c, d_data, alloc) || dev_reserve(c, d_offs, (m + 1) * 8) ||
+      dev_reserve(c, d_ch, std::max<size_t>(1, ch.size()) * sizeof(Chunk)) ||
+      dev_reserve(c, d_bm, std::max<uint64_t>(1, m * words) * 4) || dev_reserve(c, d_nnz, std::max<uint64_t>(1, m) * 8) ||
+      dev_reserve(c, d_ptr, (m + 1) * 8)) {
+    cleanup();
+    return IG_ENOMEM;
+  }
+  hipError_t e = hipMemsetAsync(reinterpret_cast<uint8_t *>(d_data.p) + need, 0, alloc - need, s);
+  if (e == hipSuccess && need) e = hipMemcpyAsync(d_data.p, data, need, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_offs.p, sym_offsets, (m + 1) * 8, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !ch.empty()) e = hipMemcpyAsync(d_ch.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(d_bm.p), std::max<uint64_t>(1, m * words), 0, s);
+  FeatBatch fb{reinterpret_cast<const uint8_t *>(d_data.p), reinterpret_cast<const uint64_t *>(d_offs.p), m,
+               reinterpret_cast<const Chunk *>(d_ch.p), (uint32_t)ch.size(), reinterpret_cast<uint32_t *>(d_bm.p), words};
+  if (e == hipSuccess && words) e = launch_featurize(c, fb, s);
+  if (e == hipSuccess && words)
+    e = launch_rows(fb.bitmaps, m, words, reinterpret_cast<uint64_t *>(d_nnz.p), nullptr, nullptr, 0, 1, s);
+  std::vector<uint64_t> nnz(m, 0);
+  if (e == hipSuccess && m && words) e = hipMemcpyAsync(nnz.data(), d_nnz.p, m * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (check_hip(c, e, "featurize")) { cleanup(); return IG_EDEVICE; }
+  indptr[0] = 0;
+  for (uint64_t i = 0; i < m; i++) indptr[i + 1] = indptr[i] + nnz[i];
+  const uint64_t total = indptr[m];
+  if (nnz_out) *nnz_out = total;
+  if (total > cap) { cleanup(); return set_error(c, IG_ETRUNC, "need %llu indices", (unsigned long long)total); }
+  if (total) {
+    if (dev_reserve(c, d_ind, total * 4)) { cleanup(); return IG_ENOMEM; }
+    e = hipMemcpyAsync(d_ptr.p, indptr, (m + 1) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_rows(fb.bitmaps, m, words, nullptr, reinterpret_cast<const uint64_t *>(d_ptr.p),
+                      reinterpret_cast<int32_t *>(d_ind.p), total, 0, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(indices, d_ind.p, total * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (check_hip(c, e, "featurize rows")) { cleanup(); return IG_EDEVICE; }
+  }
+  cleanup();
+  return IG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,208 @@
+// Internal declarations shared by the HIP sources of libintergrams.so.
+//
+// Data layout in HBM (all buffers owned by the context):
+//  * corpus: the symbol stream as loaded (bytes, or 2-bit symbols MSB first),
+//    padded with 64 zero bytes; file offsets in symbols (m+1 x u64).
+//  * work items ("chunks"): each covers at most chunk_syms symbols of one file;
+//    a chunk owns the windows that start inside it and reads the n-1 symbols
+//    after it (the halo) from the same file.  Chunks are kept in file order (for
+//    the one-launch-per-file form) and in decreasing length (the LPT order of
+//    the persistent work queue).
+//  * candidate space: a pass counts into a dense array indexed by a candidate id
+//      filtered pass:      cid = rank(prefix) * sigma + code(last symbol)
+//                          (the paper's C in N^{256 zk}, Algorithm 3, with the
+//                          alphabet compacted to the sigma symbols present)
+//      small unfiltered:   cid = key                       (n*b <= 26)
+//      large unfiltered:   cid = slot of the key in a device hash table
+//  * retained table: keys (lo/hi u64 arrays) and counts (u64), in the order
+//    (count desc, key asc); a hash map key -> rank+1 and a compact filter image
+//    over the same keys serve both the next pass (prefix test) and featurize.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ig.h"
+
+namespace ig {
+
+// ------------------------------------------------------------------ device helpers
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t hash_key(uint64_t lo, uint64_t hi) {
+  return mix64(lo ^ mix64(hi ^ 0x9E3779B97F4A7C15ull));
+}
+__host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
+  return x;
+}
+
+// ------------------------------------------------------------------ shared structs
+struct Chunk {
+  uint64_t s0;      // first symbol (absolute) whose window this chunk owns
+  uint32_t file;
+  uint32_t nsym;    // symbols owned (windows start in [s0, s0 + nsym))
+  uint32_t multi;   // the file has more than one chunk
+  uint32_t pad;
+};
+
+enum PassMode { MODE_DENSE = 0, MODE_FILTERED = 1, MODE_SPARSE = 2 };
+enum FilterKind { FILT_NONE = 0, FILT_DIRECT = 1, FILT_BLOOM = 2 };
+enum StatusBits { ST_PSET_OVF = 1u, ST_TABLE_OVF = 2u };
+
+static constexpr uint32_t LDS_EMPTY = 0xFFFFFFFFu;
+
+// Parameters of one scan (ingest + prefix filter + per-sequence dedup + count) launch.
+struct ScanParams {
+  const uint8_t *data;
+  const uint64_t *offs;          // m+1 symbol offsets
+  const Chunk *chunks;
+  uint32_t nchunks;              // chunks of this launch
+  uint32_t chunk_base;           // non-persistent launches: first chunk index
+  uint32_t *qctr;                // persistent launches: work-queue counter
+  uint32_t persistent;
+  uint32_t n;                    // gram length
+  uint32_t sigma;                // compacted alphabet size
+  const uint8_t *code;           // symbol -> code (256 entries)
+  // compact filter over the previous table's keys (copied into LDS)
+  const uint32_t *filt;
+  uint32_t filt_words;           // power of two
+  uint32_t filt_kind;
+  // exact map previous key -> rank + 1
+  const uint64_t *mkey_lo, *mkey_hi;
+  const uint32_t *mval;
+  uint64_t mmask;
+  // large unfiltered passes: key table
+  uint64_t *tkey_lo, *tkey_hi;
+  uint32_t *tstate;
+  uint64_t tmask;
+  // counts and cross-chunk de-duplication
+  void *cnt;
+  uint64_t *pset;
+  uint64_t pmask;
+  uint32_t *status;
+  uint32_t set_cap;              // LDS de-duplication set entries (power of two)
+  uint32_t stage_bytes;          // LDS staging bytes
+};
+
+// Parameters of the selection of the k_keep best candidates.
+struct SelectParams {
+  const void *cnt;
+  uint64_t nc;                   // candidate ids [0, nc)
+  int count64;                   // count array is u64
+  int mode;
+  uint32_t bits;                 // symbol bits
+  uint32_t sigma;
+  const uint8_t *sym_of_code;
+  const uint64_t *pk_lo, *pk_hi; // previous table keys (filtered mode)
+  const uint64_t *tk_lo, *tk_hi; // key table (sparse mode)
+};
+
+// ------------------------------------------------------------------ device buffers
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// One retained table and its index (exact map key -> rank+1, compact filter image).
+struct TableSet {
+  DevBuf lo, hi, cnt;
+  DevBuf map_lo, map_hi, map_val, filt;
+  uint64_t kept = 0, map_mask = 0;
+  uint32_t n = 0, filt_words = 0, filt_kind = 0;
+};
+
+struct LaunchCfg {
+  uint32_t chunk_syms = 16384;
+  uint32_t block = 512;
+  uint32_t grid_per_cu = 1;
+  uint32_t set_cap = 8192;
+  uint32_t filt_max_words = 16384;   // 64 KB of LDS
+};
+
+}  // namespace ig
+
+// ------------------------------------------------------------------ context
+struct ig_ctx {
+  ig_config cfg{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int n_cu = 256;
+  std::string err;
+  int sticky = 0;
+  uint64_t held_bytes = 0;
+
+  // corpus
+  ig::DevBuf data, offs, chunks_lpt, chunks_file, code, sym_of_code, qctr, status;
+  std::vector<uint64_t> h_offs;
+  std::vector<uint32_t> file_chunk0;   // first chunk (file order) of each file, m+1 entries
+  uint64_t m = 0, total_syms = 0, data_bytes = 0, nchunks = 0;
+  uint32_t sigma = 0;
+  uint8_t h_code[256]{}, h_sym_of_code[256]{};
+  bool loaded = false;
+  ig::LaunchCfg lc;
+
+  // pass state: three rotating table sets (current, previous, next)
+  ig::TableSet ts[3];
+  int cur = 0, prev = 1, nxt = 2;
+  bool fresh = true;            // no retained table since the last load
+  bool prev_fresh = true;       // state before the last pass (for ig_rewind)
+  bool can_rewind = false;
+  uint32_t n_prev = 0;
+  uint64_t kept = 0;
+  ig::TableSet &T() { return ts[cur]; }
+
+  // pass scratch
+  ig::DevBuf cnt, pset, tkey_lo, tkey_hi, tstate;
+  uint64_t pset_slots = 1ull << 22, tkey_slots = 0;
+  ig::DevBuf sel_cid, sel_cnt, sel_klo, sel_khi, tie_a, tie_b, sort_tmp, hist, selstate, thist;
+
+  ig_pass_stats last{};
+  hipEvent_t ev[4]{};
+
+  // featurize / serving
+  void *server = nullptr;
+};
+
+namespace ig {
+// serving loop teardown (ig_serve.hip)
+void serve_teardown(ig_ctx *c);
+// allocation helpers (ig_api.hip)
+int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes);
+void dev_release(ig_ctx *c, DevBuf &b);
+int set_error(ig_ctx *c, int code, const char *fmt, ...);
+int check_hip(ig_ctx *c, hipError_t e, const char *what);
+
+// kernels' host launchers
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ, int count64,
+                       uint32_t grid, uint32_t block, hipStream_t s);
+size_t scan_lds_bytes(const ScanParams &p, int mode, int occ);
+// selection: returns kept count via *kept (device->host sync inside)
+int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits,
+               uint64_t *kept_out);
+// map + filter over a table set
+int build_table_index(ig_ctx *c, TableSet &t);
+// featurize a device-resident batch into per-file rank bitmaps and CSR
+struct FeatBatch {
+  const uint8_t *data;       // device
+  const uint64_t *offs;      // device, m+1
+  uint64_t m;
+  const Chunk *chunks;       // device
+  uint32_t nchunks;
+  uint32_t *bitmaps;         // device, m * words
+  uint32_t words;
+};
+hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s);
+hipError_t launch_rows(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint64_t *nnz_per_row,
+                       const uint64_t *indptr, int32_t *indices, uint64_t cap, int count_only, hipStream_t s);
+hipError_t launch_col_counts(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint32_t kept,
+                             uint32_t *col_counts, hipStream_t s);
+}  // namespace ig

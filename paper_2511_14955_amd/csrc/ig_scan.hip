@@ -1,0 +1,314 @@
+// Scan kernel: one pass over the corpus (Algorithm 3's inner loops).
+//
+// For every window t of every sequence (windows never cross a sequence end):
+//   key      = the n symbols at t, first symbol most significant     (ingest)
+//   survive  = n = 1, no previous table, or (key >> b) in the table  (prefix filter)
+//   count    = once per sequence (Eq. 2) or once per occurrence (Eq. 1)
+//
+// Work items are chunks of one file; a workgroup stages a chunk (plus the
+// n-1-symbol halo read from the same file) into LDS with 16-byte coalesced
+// loads, then each thread rolls a key across a contiguous run of windows.
+// The prefix test first consults a compact filter image held in LDS (a direct
+// bitmap when the prefix space is small, otherwise a blocked Bloom filter with
+// no false negatives); only filter hits probe the exact key -> rank map.
+// Survivors become dense candidate ids.  Per-sequence de-duplication (Eq. 2)
+// uses an LDS hash set per chunk; sequences split over several chunks (or a
+// chunk whose set overflowed) go through a device-wide set of
+// (sequence, candidate) pairs so that each pair is counted once.
+#include "ig_internal.h"
+
+namespace ig {
+
+template <int KW> struct KeyT;
+template <> struct KeyT<1> {
+  uint64_t lo;
+  __device__ __forceinline__ void clear() { lo = 0; }
+  template <int B> __device__ __forceinline__ void push(uint32_t s, uint64_t mlo, uint64_t) { lo = ((lo << B) | s) & mlo; }
+  template <int B> __device__ __forceinline__ uint64_t pre_lo() const { return lo >> B; }
+  template <int B> __device__ __forceinline__ uint64_t pre_hi() const { return 0; }
+  static constexpr uint64_t hi = 0;
+};
+template <> struct KeyT<2> {
+  uint64_t lo, hi;
+  __device__ __forceinline__ void clear() { lo = 0; hi = 0; }
+  template <int B> __device__ __forceinline__ void push(uint32_t s, uint64_t, uint64_t mhi) {
+    hi = ((hi << B) | (lo >> (64 - B))) & mhi;
+    lo = (lo << B) | s;
+  }
+  template <int B> __device__ __forceinline__ uint64_t pre_lo() const { return (lo >> B) | (hi << (64 - B)); }
+  template <int B> __device__ __forceinline__ uint64_t pre_hi() const { return hi >> B; }
+};
+
+template <typename CT> __device__ __forceinline__ void cnt_add(void *cnt, uint32_t cid, CT v) {
+  __hip_atomic_fetch_add(reinterpret_cast<CT *>(cnt) + cid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-wide set of (sequence, candidate) pairs: true if the pair is new.
+__device__ __forceinline__ bool pset_insert(const ScanParams &p, uint32_t file, uint32_t cid) {
+  const uint64_t key = ((uint64_t)(file + 1) << 32) | cid;
+  uint64_t slot = mix64(key) & p.pmask;
+  for (int probe = 0; probe < 4096; probe++) {
+    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(p.pset + slot), 0ull,
+                                       (unsigned long long)key);
+    if (old == 0ull) return true;
+    if (old == key) return false;
+    slot = (slot + 1) & p.pmask;
+  }
+  atomicOr(p.status, ST_PSET_OVF);
+  return false;
+}
+
+// Exact lookup in the key -> rank+1 map (capacity >= 2x entries, so a probe run ends).
+template <int KW>
+__device__ __forceinline__ int64_t map_find(const ScanParams &p, uint64_t lo, uint64_t hi, uint64_t h) {
+  uint64_t slot = h & p.mmask;
+  for (;;) {
+    const uint32_t v = p.mval[slot];
+    if (v == 0) return -1;
+    if (p.mkey_lo[slot] == lo && (KW == 1 || p.mkey_hi[slot] == hi)) return (int64_t)v - 1;
+    slot = (slot + 1) & p.mmask;
+  }
+}
+
+// Insert-or-find in the key table of large unfiltered passes; returns the slot,
+// or 0xFFFFFFFF after flagging an overflow.  A slot is claimed (state 0 -> 1),
+// its key words written, then published (state 2); readers wait on state 1.
+__device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t lo, uint64_t hi) {
+  uint64_t slot = hash_key(lo, hi) & p.tmask;
+  uint32_t probes = 0;
+  for (uint32_t iter = 0; iter < (1u << 22); iter++) {
+    uint32_t st = __hip_atomic_load(p.tstate + slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (st == 0) {
+      uint32_t expect = 0;
+      if (__hip_atomic_compare_exchange_strong(p.tstate + slot, &expect, 1u, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        __hip_atomic_store(p.tkey_lo + slot, lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p.tkey_hi + slot, hi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(p.tstate + slot, 2u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return (uint32_t)slot;
+      }
+      continue;
+    }
+    if (st == 1) continue;  // being published by another thread
+    const uint64_t klo = __hip_atomic_load(p.tkey_lo + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t khi = __hip_atomic_load(p.tkey_hi + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (klo == lo && khi == hi) return (uint32_t)slot;
+    slot = (slot + 1) & p.tmask;
+    if (++probes > 4096) break;
+  }
+  atomicOr(p.status, ST_TABLE_OVF);
+  return 0xFFFFFFFFu;
+}
+
+// LDS open-addressing set of candidate ids: 1 = newly inserted, 0 = present, -1 = full.
+__device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t cid, uint32_t *slot_out) {
+  uint32_t h = hash32(cid) & capmask;
+  for (int i = 0; i < 64; i++) {
+    const uint32_t old = atomicCAS(s_set + h, LDS_EMPTY, cid);
+    if (old == LDS_EMPTY) { *slot_out = h; return 1; }
+    if (old == cid) { *slot_out = h; return 0; }
+    h = (h + 1) & capmask;
+  }
+  return -1;
+}
+
+template <int B>
+__device__ __forceinline__ uint32_t stage_sym(const uint8_t *s_stage, uint64_t g, uint64_t a0) {
+  if (B == 8) return s_stage[g - a0];
+  const uint32_t byte = s_stage[(g >> 2) - a0];
+  return (byte >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
+}
+
+template <int B, int KW, int MODE, int OCC, typename CT>
+__global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  uint8_t *s_stage = lds;
+  uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
+  uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? p.filt_words : 0);
+  uint32_t *s_cnt = s_set + p.set_cap;                 // OCC only
+  uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
+  __shared__ uint32_t s_chunk, s_over;
+
+  const uint32_t tid = threadIdx.x, bs = blockDim.x;
+  const uint32_t n = p.n;
+  const uint32_t nb = n * B;
+  const uint64_t mlo = (KW == 1) ? (nb >= 64 ? ~0ull : ((1ull << nb) - 1)) : ~0ull;
+  const uint64_t mhi = (KW == 2) ? (nb >= 128 ? ~0ull : ((1ull << (nb - 64)) - 1)) : 0ull;
+  const uint32_t capmask = p.set_cap - 1;
+  const uint32_t fmask = p.filt_words - 1;
+
+  if (MODE == MODE_FILTERED)
+    for (uint32_t i = tid; i < p.filt_words; i += bs) s_filt[i] = p.filt[i];
+  for (uint32_t i = tid; i < p.set_cap; i += bs) {
+    s_set[i] = LDS_EMPTY;
+    if (OCC) s_cnt[i] = 0;
+  }
+  for (uint32_t i = tid; i < 256; i += bs) s_code[i] = p.code[i];
+  __syncthreads();
+
+  uint32_t local_iter = 0;
+  for (;;) {
+    if (tid == 0) {
+      if (p.persistent) s_chunk = atomicAdd(p.qctr, 1u);
+      else s_chunk = local_iter == 0 ? p.chunk_base + blockIdx.x : 0xFFFFFFFFu;
+      s_over = 0;
+    }
+    __syncthreads();
+    const uint32_t ci = s_chunk;
+    local_iter++;
+    if (ci == 0xFFFFFFFFu || (p.persistent ? ci >= p.nchunks : ci >= p.chunk_base + p.nchunks)) break;
+    const Chunk c = p.chunks[ci];
+    const uint64_t fend = p.offs[c.file + 1];
+    const uint64_t flen = fend - p.offs[c.file];
+    const uint64_t wbeg = c.s0;
+    uint64_t wend = c.s0 + c.nsym;
+    if (flen < n) wend = wbeg;
+    else if (wend > fend - n + 1) wend = fend - n + 1;
+    if (wbeg >= wend) { __syncthreads(); continue; }
+    const uint64_t nwin = wend - wbeg;
+
+    // stage [wbeg, wend + n - 1) symbols with 16-byte loads
+    const uint64_t byte_lo = (B == 8) ? wbeg : (wbeg >> 2);
+    const uint64_t byte_hi = (B == 8) ? (wend + n - 1) : ((wend + n - 2) >> 2) + 1;
+    const uint64_t a0 = byte_lo & ~15ull;
+    const uint64_t a1 = (byte_hi + 15) & ~15ull;
+    const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
+    for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs) reinterpret_cast<uint4 *>(s_stage)[i] = src[i];
+    __syncthreads();
+
+    const uint32_t per = (uint32_t)((nwin + bs - 1) / bs);
+    const uint64_t t_lo = (uint64_t)tid * per;
+    const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
+    if (t_lo < t_hi) {
+      KeyT<KW> k;
+      k.clear();
+      const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
+      const uint64_t sbase = (B == 8) ? a0 : a0;
+      for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
+      for (uint64_t t = t_lo; t < t_hi; t++) {
+        const uint64_t g = wbeg + t;
+        k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
+        uint32_t cid;
+        if (MODE == MODE_DENSE) {
+          cid = (uint32_t)k.lo;
+        } else if (MODE == MODE_FILTERED) {
+          const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
+          uint64_t h = 0;
+          if (p.filt_kind == FILT_DIRECT) {
+            if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
+            h = hash_key(plo, phi);
+          } else {
+            h = hash_key(plo, phi);
+            if (p.filt_kind == FILT_BLOOM) {
+              const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
+              const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+              if ((w & bm) != bm) continue;
+            }
+          }
+          const int64_t r = map_find<KW>(p, plo, phi, h);
+          if (r < 0) continue;
+          const uint32_t last = (uint32_t)(k.lo & ((1u << B) - 1));
+          cid = (uint32_t)r * p.sigma + s_code[last];
+        } else {
+          cid = table_insert(p, k.lo, k.hi);
+          if (cid == 0xFFFFFFFFu) continue;
+        }
+        uint32_t slot;
+        const int ins = lds_insert(s_set, capmask, cid, &slot);
+        if (OCC) {
+          if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
+          else cnt_add<CT>(p.cnt, cid, (CT)1);
+        } else if (ins < 0) {
+          s_over = 1;
+          if (pset_insert(p, c.file, cid)) cnt_add<CT>(p.cnt, cid, (CT)1);
+        }
+      }
+    }
+    __syncthreads();
+    const bool direct = !c.multi && !s_over;
+    for (uint32_t i = tid; i < p.set_cap; i += bs) {
+      const uint32_t cid = s_set[i];
+      if (cid == LDS_EMPTY) continue;
+      if (OCC) {
+        cnt_add<CT>(p.cnt, cid, (CT)s_cnt[i]);
+        s_cnt[i] = 0;
+      } else if (direct || pset_insert(p, c.file, cid)) {
+        cnt_add<CT>(p.cnt, cid, (CT)1);
+      }
+      s_set[i] = LDS_EMPTY;
+    }
+    __syncthreads();
+  }
+}
+
+size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
+  size_t b = p.stage_bytes;
+  if (mode == MODE_FILTERED) b += (size_t)p.filt_words * 4;
+  b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
+  b += 256;
+  return b;
+}
+
+template <int B, int KW, int MODE, int OCC, typename CT>
+static hipError_t launch_t(const ScanParams &p, uint32_t grid, uint32_t block, hipStream_t s) {
+  const size_t lds = scan_lds_bytes(p, MODE, OCC);
+  auto fn = k_scan<B, KW, MODE, OCC, CT>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, p);
+  return hipGetLastError();
+}
+
+template <int B, int KW, int MODE>
+static hipError_t launch_m(const ScanParams &p, int occ, int count64, uint32_t grid, uint32_t block, hipStream_t s) {
+  if (!occ) return launch_t<B, KW, MODE, 0, uint32_t>(p, grid, block, s);
+  if (!count64) return launch_t<B, KW, MODE, 1, uint32_t>(p, grid, block, s);
+  return launch_t<B, KW, MODE, 1, unsigned long long>(p, grid, block, s);
+}
+
+hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ, int count64, uint32_t grid,
+                       uint32_t block, hipStream_t s) {
+  if (bits == 8) {
+    if (mode == MODE_DENSE) return launch_m<8, 1, MODE_DENSE>(p, occ, count64, grid, block, s);
+    if (kw == 1) {
+      if (mode == MODE_FILTERED) return launch_m<8, 1, MODE_FILTERED>(p, occ, count64, grid, block, s);
+      return launch_m<8, 1, MODE_SPARSE>(p, occ, count64, grid, block, s);
+    }
+    if (mode == MODE_FILTERED) return launch_m<8, 2, MODE_FILTERED>(p, occ, count64, grid, block, s);
+    return launch_m<8, 2, MODE_SPARSE>(p, occ, count64, grid, block, s);
+  }
+  if (mode == MODE_DENSE) return launch_m<2, 1, MODE_DENSE>(p, occ, count64, grid, block, s);
+  if (kw == 1) {
+    if (mode == MODE_FILTERED) return launch_m<2, 1, MODE_FILTERED>(p, occ, count64, grid, block, s);
+    return launch_m<2, 1, MODE_SPARSE>(p, occ, count64, grid, block, s);
+  }
+  if (mode == MODE_FILTERED) return launch_m<2, 2, MODE_FILTERED>(p, occ, count64, grid, block, s);
+  return launch_m<2, 2, MODE_SPARSE>(p, occ, count64, grid, block, s);
+}
+
+// ------------------------------------------------------------------ fills (graph-safe, no memset nodes)
+__global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)g), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  uint64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)g), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace ig

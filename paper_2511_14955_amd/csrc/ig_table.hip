@@ -1,0 +1,303 @@
+// Index over the retained table, and featurization against it.
+//
+// After a pass (Algorithm 3's "P^(j) <- zk-argmax") the retained keys are
+// indexed twice:
+//  * an exact open-addressing map key -> rank+1 (capacity a power of two, at
+//    least twice the table), probed only by filter hits;
+//  * a compact filter image that a scan workgroup copies into LDS: a direct
+//    bitmap over the whole key space when it is small enough (exact), else a
+//    blocked Bloom filter (three bits in one 32-bit word chosen by the key hash;
+//    no false negatives).
+// The same index answers the prefix test of the next pass (the prefix of an
+// (n+1)-window is an n-gram) and the lookups of featurize (Figure 1's Boolean
+// m x k matrix).
+//
+// Featurize: each workgroup takes a chunk of one sequence, rolls n-gram keys
+// over it, and sets bit rank(key) in an LDS bitmap of kept bits; at the end of
+// the chunk the non-zero words are OR-ed into the sequence's bitmap in HBM
+// (word-contiguous, so the atomics coalesce).  A sequence's row is then the set
+// bits of its bitmap in increasing order: de-duplicated and sorted by
+// construction.
+#include "ig_internal.h"
+
+namespace ig {
+
+__global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, uint64_t kept, uint64_t *mlo, uint64_t *mhi,
+                             uint32_t *mval, uint64_t mmask) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = tlo[i], hi = thi[i];
+    uint64_t slot = hash_key(lo, hi) & mmask;
+    for (;;) {
+      if (atomicCAS(mval + slot, 0u, (uint32_t)(i + 1)) == 0u) {
+        mlo[slot] = lo;
+        mhi[slot] = hi;
+        break;
+      }
+      slot = (slot + 1) & mmask;
+    }
+  }
+}
+
+__global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, uint64_t kept, uint32_t *filt, uint32_t words,
+                               uint32_t kind) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = tlo[i], hi = thi[i];
+    if (kind == FILT_DIRECT) {
+      atomicOr(filt + (lo >> 5), 1u << (lo & 31));
+    } else {
+      const uint64_t h = hash_key(lo, hi);
+      const uint32_t w = (uint32_t)(((h >> 32) * (uint64_t)words) >> 32);
+      atomicOr(filt + w, (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31)));
+    }
+  }
+}
+
+int build_table_index(ig_ctx *c, TableSet &ts) {
+  hipStream_t s = c->stream;
+  const uint64_t kept = ts.kept;
+  uint64_t cap = 1024;
+  while (cap < 2 * kept) cap <<= 1;
+  const uint32_t nbits = ts.n * c->cfg.symbol_bits;
+  const uint64_t maxw = c->lc.filt_max_words;
+  uint32_t kind, words;
+  if (nbits <= 40 && (1ull << nbits) <= maxw * 32) {
+    kind = FILT_DIRECT;
+    words = (uint32_t)(((1ull << nbits) + 31) / 32);
+  } else {
+    kind = FILT_BLOOM;
+    uint64_t w = (kept * 12 + 31) / 32;
+    if (w < 64) w = 64;
+    if (w > maxw) w = maxw;
+    words = (uint32_t)w;
+  }
+  if (dev_reserve(c, ts.map_lo, cap * 8) || dev_reserve(c, ts.map_hi, cap * 8) || dev_reserve(c, ts.map_val, cap * 4) ||
+      dev_reserve(c, ts.filt, (uint64_t)words * 4))
+    return IG_ENOMEM;
+  ts.map_mask = cap - 1;
+  ts.filt_words = words;
+  ts.filt_kind = kind;
+  if (launch_fill_u32(reinterpret_cast<uint32_t *>(ts.map_val.p), cap, 0, s) != hipSuccess ||
+      launch_fill_u32(reinterpret_cast<uint32_t *>(ts.filt.p), words, 0, s) != hipSuccess)
+    return check_hip(c, hipGetLastError(), "index fill") ? IG_EDEVICE : IG_EDEVICE;
+  if (kept) {
+    uint64_t g = (kept + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
+                       reinterpret_cast<const uint64_t *>(ts.hi.p), kept, reinterpret_cast<uint64_t *>(ts.map_lo.p),
+                       reinterpret_cast<uint64_t *>(ts.map_hi.p), reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask);
+    hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s,
+                       reinterpret_cast<const uint64_t *>(ts.lo.p), reinterpret_cast<const uint64_t *>(ts.hi.p),
+                       kept, reinterpret_cast<uint32_t *>(ts.filt.p), words, kind);
+  }
+  return check_hip(c, hipGetLastError(), "index build") ? IG_EDEVICE : IG_OK;
+}
+
+// ------------------------------------------------------------------ featurize
+struct FeatParams {
+  const uint8_t *data;
+  const uint64_t *offs;
+  const Chunk *chunks;
+  uint32_t nchunks;
+  uint32_t n;
+  const uint32_t *filt;
+  uint32_t filt_words, filt_kind;
+  const uint64_t *mkey_lo, *mkey_hi;
+  const uint32_t *mval;
+  uint64_t mmask;
+  uint32_t *bitmaps;
+  uint32_t words;        // per-sequence bitmap words (ceil(kept / 32))
+  uint32_t lds_bitmap;   // the bitmap fits in LDS
+  uint32_t stage_bytes;
+};
+
+template <int B, int KW>
+__global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  uint8_t *s_stage = lds;
+  uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
+  uint32_t *s_bm = s_filt + p.filt_words;
+  const uint32_t tid = threadIdx.x, bs = blockDim.x, n = p.n, nb = n * B;
+  const uint64_t mlo = (KW == 1) ? (nb >= 64 ? ~0ull : ((1ull << nb) - 1)) : ~0ull;
+  const uint64_t mhi = (KW == 2) ? (nb >= 128 ? ~0ull : ((1ull << (nb - 64)) - 1)) : 0ull;
+  for (uint32_t i = tid; i < p.filt_words; i += bs) s_filt[i] = p.filt[i];
+  if (p.lds_bitmap)
+    for (uint32_t i = tid; i < p.words; i += bs) s_bm[i] = 0;
+  __syncthreads();
+  for (uint32_t ci = blockIdx.x; ci < p.nchunks; ci += gridDim.x) {
+    const Chunk c = p.chunks[ci];
+    const uint64_t fend = p.offs[c.file + 1], flen = fend - p.offs[c.file];
+    uint32_t *gbm = p.bitmaps + (uint64_t)c.file * p.words;
+    const uint64_t wbeg = c.s0;
+    uint64_t wend = c.s0 + c.nsym;
+    if (flen < n) wend = wbeg;
+    else if (wend > fend - n + 1) wend = fend - n + 1;
+    if (wbeg < wend) {
+      const uint64_t nwin = wend - wbeg;
+      const uint64_t byte_lo = (B == 8) ? wbeg : (wbeg >> 2);
+      const uint64_t byte_hi = (B == 8) ? (wend + n - 1) : ((wend + n - 2) >> 2) + 1;
+      const uint64_t a0 = byte_lo & ~15ull, a1 = (byte_hi + 15) & ~15ull;
+      const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
+      for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs) reinterpret_cast<uint4 *>(s_stage)[i] = src[i];
+      __syncthreads();
+      const uint32_t per = (uint32_t)((nwin + bs - 1) / bs);
+      const uint64_t t_lo = (uint64_t)tid * per, t_hi = t_lo + per < nwin ? t_lo + per : nwin;
+      if (t_lo < t_hi) {
+        uint64_t klo = 0, khi = 0;
+        auto sym = [&](uint64_t g) -> uint32_t {
+          if (B == 8) return s_stage[g - a0];
+          return (s_stage[(g >> 2) - a0] >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
+        };
+        auto push = [&](uint32_t sv) {
+          if (KW == 2) {
+            khi = ((khi << B) | (klo >> (64 - B))) & mhi;
+            klo = (klo << B) | sv;
+          } else {
+            klo = ((klo << B) | sv) & mlo;
+          }
+        };
+        for (uint32_t r = 0; r + 1 < n; r++) push(sym(wbeg + t_lo + r));
+        for (uint64_t t = t_lo; t < t_hi; t++) {
+          push(sym(wbeg + t + n - 1));
+          const uint64_t h = hash_key(klo, khi);
+          if (p.filt_kind == FILT_DIRECT) {
+            if (!((s_filt[klo >> 5] >> (klo & 31)) & 1u)) continue;
+          } else {
+            const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
+            const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+            if ((w & bm) != bm) continue;
+          }
+          uint64_t slot = h & p.mmask;
+          int64_t r = -1;
+          for (;;) {
+            const uint32_t v = p.mval[slot];
+            if (!v) break;
+            if (p.mkey_lo[slot] == klo && p.mkey_hi[slot] == khi) { r = (int64_t)v - 1; break; }
+            slot = (slot + 1) & p.mmask;
+          }
+          if (r < 0) continue;
+          if (p.lds_bitmap) atomicOr(s_bm + (r >> 5), 1u << (r & 31));
+          else atomicOr(gbm + (r >> 5), 1u << (r & 31));
+        }
+      }
+      __syncthreads();
+      if (p.lds_bitmap) {
+        for (uint32_t i = tid; i < p.words; i += bs) {
+          const uint32_t v = s_bm[i];
+          if (v) { atomicOr(gbm + i, v); s_bm[i] = 0; }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s) {
+  FeatParams p{};
+  p.data = fb.data;
+  p.offs = fb.offs;
+  p.chunks = fb.chunks;
+  p.nchunks = fb.nchunks;
+  const TableSet &ts = c->ts[c->cur];
+  p.n = ts.n;
+  p.filt = reinterpret_cast<const uint32_t *>(ts.filt.p);
+  p.filt_words = ts.filt_words;
+  p.filt_kind = ts.filt_kind;
+  p.mkey_lo = reinterpret_cast<const uint64_t *>(ts.map_lo.p);
+  p.mkey_hi = reinterpret_cast<const uint64_t *>(ts.map_hi.p);
+  p.mval = reinterpret_cast<const uint32_t *>(ts.map_val.p);
+  p.mmask = ts.map_mask;
+  p.bitmaps = fb.bitmaps;
+  p.words = fb.words;
+  const uint32_t bits = c->cfg.symbol_bits;
+  p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * bits / 8 + 64 + 32) & ~15ull);
+  const size_t base = p.stage_bytes + (size_t)p.filt_words * 4;
+  const size_t limit = 160 * 1024 - 512;
+  p.lds_bitmap = base + (size_t)p.words * 4 <= limit ? 1u : 0u;
+  const size_t lds = base + (p.lds_bitmap ? (size_t)p.words * 4 : 0);
+  if (!fb.nchunks) return hipSuccess;
+  uint32_t grid = fb.nchunks < (uint32_t)c->n_cu * 2 ? fb.nchunks : (uint32_t)c->n_cu * 2;
+  const bool kw2 = (uint64_t)p.n * bits > 64;
+  const void *fn;
+  if (bits == 8) fn = kw2 ? reinterpret_cast<const void *>(k_featurize<8, 2>) : reinterpret_cast<const void *>(k_featurize<8, 1>);
+  else fn = kw2 ? reinterpret_cast<const void *>(k_featurize<2, 2>) : reinterpret_cast<const void *>(k_featurize<2, 1>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (bits == 8) {
+    if (kw2) hipLaunchKernelGGL((k_featurize<8, 2>), dim3(grid), dim3(512), lds, s, p);
+    else hipLaunchKernelGGL((k_featurize<8, 1>), dim3(grid), dim3(512), lds, s, p);
+  } else {
+    if (kw2) hipLaunchKernelGGL((k_featurize<2, 2>), dim3(grid), dim3(512), lds, s, p);
+    else hipLaunchKernelGGL((k_featurize<2, 1>), dim3(grid), dim3(512), lds, s, p);
+  }
+  return hipGetLastError();
+}
+
+// one workgroup per row: popcount (count_only) or write the set-bit positions in order
+__global__ void __launch_bounds__(256) k_rows(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint64_t *nnz,
+                                              const uint64_t *indptr, int32_t *indices, uint64_t cap, int count_only) {
+  __shared__ uint32_t part[256];
+  const uint32_t t = threadIdx.x;
+  for (uint64_t f = blockIdx.x; f < m; f += gridDim.x) {
+    const uint32_t *bm = bitmaps + f * words;
+    const uint32_t per = (words + 255) / 256;
+    const uint32_t lo = t * per, hi = lo + per < words ? lo + per : words;
+    uint32_t cntl = 0;
+    for (uint32_t w = lo; w < hi; w++) cntl += __popc(bm[w]);
+    part[t] = cntl;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+      const uint32_t v = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    if (count_only) {
+      if (t == 255) nnz[f] = part[255];
+    } else {
+      uint64_t pos = indptr[f] + part[t] - cntl;
+      for (uint32_t w = lo; w < hi; w++) {
+        uint32_t v = bm[w];
+        while (v) {
+          const uint32_t b = __ffs(v) - 1;
+          v &= v - 1;
+          if (pos < cap) indices[pos] = (int32_t)(w * 32 + b);
+          pos++;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_rows(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint64_t *nnz_per_row, const uint64_t *indptr,
+                       int32_t *indices, uint64_t cap, int count_only, hipStream_t s) {
+  if (!m) return hipSuccess;
+  const uint32_t grid = m < 4096 ? (uint32_t)m : 4096;
+  hipLaunchKernelGGL(k_rows, dim3(grid), dim3(256), 0, s, bitmaps, m, words, nnz_per_row, indptr, indices, cap,
+                     count_only);
+  return hipGetLastError();
+}
+
+// number of the m sequences whose bitmap has each bit set (count requests)
+__global__ void k_col_counts(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint32_t kept, uint32_t *out) {
+  for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < words; w += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t acc[32];
+    for (int b = 0; b < 32; b++) acc[b] = 0;
+    for (uint64_t f = 0; f < m; f++) {
+      const uint32_t v = bitmaps[f * words + w];
+      for (int b = 0; b < 32; b++) acc[b] += (v >> b) & 1u;
+    }
+    for (int b = 0; b < 32; b++)
+      if (w * 32 + b < kept) out[w * 32 + b] = acc[b];
+  }
+}
+
+hipError_t launch_col_counts(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint32_t kept, uint32_t *col_counts,
+                             hipStream_t s) {
+  if (!words) return hipSuccess;
+  const uint32_t grid = (words + 255) / 256;
+  hipLaunchKernelGGL(k_col_counts, dim3(grid), dim3(256), 0, s, bitmaps, m, words, kept, col_counts);
+  return hipGetLastError();
+}
+
+}  // namespace ig

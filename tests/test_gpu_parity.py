@@ -1,0 +1,168 @@
+"""Parity of the HIP path with the CPU oracle (bit-exact: same grams, counts, order).
+
+Each case prints what it runs before touching the GPU.  Sizes are small enough
+for the oracle to finish in seconds while spanning many chunks, multi-chunk
+files, ragged tails, both symbol widths, both key widths and both frequencies.
+"""
+import os
+import random
+
+import numpy as np
+import pytest
+
+import gen
+from helpers import assert_tables_equal, gpu_tables, oracle_tables
+
+pytestmark = pytest.mark.gpu
+
+ig = pytest.importorskip("paper_2511_14955_amd")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("occ", [False, True])
+def test_hand_worked_chain(golden_dir, occ):
+    from test_oracle_pins import read_hand
+    files, k_keep, exp = read_hand(golden_dir)
+    say("hand example", "occ" if occ else "doc")
+    got, _ = gpu_tables(gen.from_files(files), [1, 2, 3], k_keep, occ)
+    mode = "occ" if occ else "doc"
+    for n, (keys, counts) in zip([1, 2, 3], got):
+        grams = [(bytes(((int(k) >> (8 * (n - 1 - r))) & 255) for r in range(n)), int(c)) for k, c in zip(keys[:, 0], counts)]
+        assert grams == exp[mode][n]
+
+
+@pytest.mark.parametrize("bits", [8, 2])
+@pytest.mark.parametrize("occ", [False, True])
+def test_random_tiny_corpora(bits, occ):
+    rng = random.Random(77 + bits + occ)
+    for trial in range(12):
+        m = rng.randint(0, 7)
+        sigma = rng.choice([2, 3, 4] if bits == 2 else [2, 3, 5, 256])
+        files = [bytes(rng.randrange(sigma) for _ in range(rng.choice([0, 1, 3, rng.randint(0, 60)]))) for _ in range(m)]
+        nmax = rng.randint(1, 8 if bits == 8 else 40)
+        ns = list(range(1, nmax + 1))
+        k = rng.choice([1, 3, 10, 1000])
+        corpus = gen.from_files(files, bits)
+        say("tiny", bits, occ, trial, m, nmax, k)
+        exp, _ = oracle_tables(corpus, ns, k, occ, nthreads=2)
+        got, g = gpu_tables(corpus, ns, k, occ)
+        assert_tables_equal(got, exp, "tiny trial %d" % trial)
+        g.close()
+
+
+@pytest.mark.parametrize("occ", [False, True])
+def test_workload1_full(occ):
+    corpus = gen.workload(1)
+    say("workload 1 full, n=1..4, k=1000", "occ" if occ else "doc")
+    exp, _ = oracle_tables(corpus, [1, 2, 3, 4], 1000, occ)
+    got, _ = gpu_tables(corpus, [1, 2, 3, 4], 1000, occ)
+    assert_tables_equal(got, exp, "workload1")
+
+
+@pytest.mark.parametrize("m,k", [(96, 100000), (160, 2000)])
+def test_workload2_sample(m, k):
+    corpus = gen.workload(2, m=m)
+    ns = list(range(1, 9))
+    say("workload 2 first %d files (%d bytes), n=1..8, k=%d" % (m, corpus.nbytes, k))
+    exp, _ = oracle_tables(corpus, ns, k)
+    got, _ = gpu_tables(corpus, ns, k)
+    assert_tables_equal(got, exp, "workload2 m=%d" % m)
+
+
+def test_workload2_occ_sample():
+    corpus = gen.workload(2, m=64)
+    ns = list(range(1, 9))
+    say("workload 2 first 64 files, Eq. 1")
+    exp, _ = oracle_tables(corpus, ns, 50000, occ=True)
+    got, _ = gpu_tables(corpus, ns, 50000, occ=True)
+    assert_tables_equal(got, exp, "workload2 occ")
+
+
+@pytest.mark.parametrize("m,k", [(300, 1000000), (400, 3000)])
+def test_workload3_sample_128bit_keys(m, k):
+    corpus = gen.workload(3, m=m)
+    ns = list(range(1, 17))
+    say("workload 3 first %d docs (%d bytes), n=1..16, k=%d" % (m, corpus.nbytes, k))
+    exp, _ = oracle_tables(corpus, ns, k)
+    got, _ = gpu_tables(corpus, ns, k)
+    assert_tables_equal(got, exp, "workload3 m=%d" % m)
+
+
+@pytest.mark.parametrize("m,k", [(12, 1000000), (20, 5000)])
+def test_workload4_sample_2bit(m, k):
+    corpus = gen.workload(4, m=m)
+    ns = list(range(1, 32))
+    say("workload 4 first %d reads (%d bases), n=1..31, k=%d" % (m, int(corpus.offsets[-1]), k))
+    exp, _ = oracle_tables(corpus, ns, k)
+    got, _ = gpu_tables(corpus, ns, k)
+    assert_tables_equal(got, exp, "workload4 m=%d" % m)
+
+
+def test_per_file_form_equals_persistent():
+    corpus = gen.workload(2, m=48)
+    ns = list(range(1, 7))
+    say("per-file launch form vs persistent, workload 2 first 48 files")
+    a, _ = gpu_tables(corpus, ns, 20000)
+    b, _ = gpu_tables(corpus, ns, 20000, flags=ig.FLAG_PER_FILE)
+    assert_tables_equal(b, a, "per-file vs persistent")
+
+
+def test_fresh_unfiltered_large_n():
+    # a pass right after loading is unfiltered at any n: 5-byte keys and 40-symbol DNA keys
+    corpus = gen.workload(2, m=8)
+    say("fresh unfiltered n=5 bytes")
+    exp, _ = oracle_tables(corpus, [5], 3000)
+    got, _ = gpu_tables(corpus, [5], 3000)
+    assert_tables_equal(got, exp, "fresh n=5")
+    c4 = gen.workload(4, m=3)
+    say("fresh unfiltered n=40 DNA (80-bit keys)")
+    exp, _ = oracle_tables(c4, [40, 41], 500)
+    got, _ = gpu_tables(c4, [40, 41], 500)
+    assert_tables_equal(got, exp, "fresh n=40 dna")
+
+
+def test_edge_cases():
+    cases = [
+        ("empty corpus", [], [1, 2], 10),
+        ("all files shorter than n", [b"ab", b"c", b""], [1, 2, 3], 10),
+        ("one repeated symbol", [b"\x07" * 5000], [1, 2, 3, 4], 5),
+        ("k_keep = 1", [b"abracadabra", b"cadabra"], [1, 2, 3], 1),
+        ("16-byte grams", [bytes(range(40)) * 3, bytes(range(5, 45)) * 2], list(range(1, 17)), 100),
+    ]
+    for name, files, ns, k in cases:
+        say("edge:", name)
+        c = gen.from_files(files)
+        exp, _ = oracle_tables(c, ns, k, nthreads=1)
+        got, _ = gpu_tables(c, ns, k)
+        assert_tables_equal(got, exp, name)
+
+
+def test_featurize_matches_oracle():
+    corpus = gen.workload(2, m=64)
+    say("featurize against the n=6 table of workload 2 (64 files)")
+    _, o = oracle_tables(corpus, list(range(1, 7)), 4000)
+    _, g = gpu_tables(corpus, list(range(1, 7)), 4000)
+    queries = gen.workload(2, m=80)
+    qs = gen.from_files([queries.file(i) for i in range(64, 80)] + [b"", b"abc"])
+    ip_o, ind_o = o.featurize(qs)
+    ip_g, ind_g = g.featurize(qs)
+    assert np.array_equal(ip_o.astype(np.uint64), ip_g)
+    assert np.array_equal(ind_o, ind_g)
+
+
+def test_errors_and_state():
+    g = ig.Intergrams()
+    with pytest.raises(ig.IGError) as e:
+        g.pass_(1, 10)
+    assert e.value.code == ig.IG_ESTATE
+    g.load(gen.from_files([b"abcdef"]))
+    assert g.try_pass(0, 5) == ig.IG_EINVAL
+    assert g.try_pass(17, 5) == ig.IG_EINVAL
+    assert g.try_pass(2, 0) == ig.IG_EINVAL
+    assert g.try_pass(2, 5) == 0
+    assert g.try_pass(4, 5) == ig.IG_ESTATE
+    assert g.try_pass(3, 5) == 0
+    assert g.table_info() == (3, 4)
