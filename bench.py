@@ -1,0 +1,144 @@
+"""Benchmark: input GB/s of one Intergrams pass (n=8, k_keep=1e5, Eq. 2) on the
+binary-like corpus (16,384 files, lognormal sizes, ~3.24 GB), one MI355X.
+
+A step is one full pass over the HBM-resident corpus: scan (ingest, prefix
+filter, per-file de-duplication, counting), selection of the top k_keep and the
+index build for the next pass.  Passes n=1..7 run first to build the retained
+set the n=8 pass filters against; each step then rewinds to that set (a pointer
+swap) and runs pass 8 again.
+
+Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n, k_keep, sample_files, threads):
+    """The CPU oracle as it stands, on the first sample_files files of the same corpus."""
+    import gen
+    import oracle
+    corpus = gen.workload(2, m=sample_files, nthreads=threads)
+    o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=threads)
+    o.load(corpus)
+    for j in range(1, n):
+        assert o.pass_(j, k_keep) == 0
+    t0 = time.perf_counter()
+    assert o.pass_(n, k_keep) == 0
+    dt = time.perf_counter() - t0
+    return {"value": round(corpus.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "pass n=%d, k_keep=%d over the first %d files of the corpus (%d bytes), after its own passes 1..%d; "
+                      "%.2f s" % (n, k_keep, sample_files, corpus.nbytes, n - 1, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=None, help="files (default: all 16,384)")
+    ap.add_argument("--n", type=int, default=8)
+    ap.add_argument("--k", type=int, default=100000)
+    ap.add_argument("--cpu-sample-files", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-file", action="store_true", help="skip the one-launch-per-file comparison")
+    ap.add_argument("--flags", type=int, default=0)
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the Intergrams pass is measured on a single MI355X; "
+              "--gpus %d is not supported" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import gen
+    import paper_2511_14955_amd as ig
+
+    threads = min(16, os.cpu_count() or 1)
+    t0 = time.time()
+    corpus = gen.workload(2, m=a.m, nthreads=threads)
+    log("workload 2: %d files, %d bytes, generated in %.1fs" % (corpus.m, corpus.nbytes, time.time() - t0))
+
+    g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags)
+    g.load(corpus)
+    for j in range(1, a.n):
+        g.pass_(j, a.k)
+        st = g.last_stats()
+        log("pass %d: %.3f ms (scan %.3f ms, select %.3f ms), kept %d, distinct %d, records %d" % (
+            j, st["pass_ms"], st["scan_ms"], st["select_ms"], g.table_info()[1], st["distinct"], st["records"]))
+    # first pass n (not timed) so that every step can rewind to the n-1 table
+    g.pass_(a.n, a.k)
+    for _ in range(a.warmup):
+        g.rewind()
+        g.pass_(a.n, a.k)
+    scan_ms, pass_ms = [], []
+    t_start = time.perf_counter()
+    for _ in range(a.steps):
+        g.rewind()
+        g.pass_(a.n, a.k)
+        st = g.last_stats()
+        scan_ms.append(st["scan_ms"])
+        pass_ms.append(st["pass_ms"])
+    t_end = time.perf_counter()
+    ms_per_step = (t_end - t_start) * 1e3 / a.steps
+    st = g.last_stats()
+    value = corpus.nbytes / (ms_per_step * 1e-3) / 1e9
+    scan_avg = sum(scan_ms) / len(scan_ms)
+    # algorithmic bytes of one scan launch: the corpus once plus the (n-1)-symbol halo of every chunk
+    nchunks = int(sum(-(-int(L) // st["chunk_syms"]) for L in (corpus.offsets[1:] - corpus.offsets[:-1])))
+    algo_bytes = corpus.nbytes + nchunks * (a.n - 1)
+    achieved = algo_bytes / (scan_avg * 1e-3) / 1e9
+    log("pass %d: %.3f ms/step wall, device pass %.3f ms, scan %.3f ms, %.1f GB/s" % (
+        a.n, ms_per_step, sum(pass_ms) / len(pass_ms), scan_avg, value))
+
+    extra = {"device_pass_ms": round(sum(pass_ms) / len(pass_ms), 4), "scan_ms": round(scan_avg, 4),
+             "select_ms": round(st["select_ms"], 4), "windows": st["windows"], "distinct_counted": st["distinct"],
+             "split_file_records": st["records"],
+             "launch": {"chunk_syms": st["chunk_syms"], "block": st["block"], "grid": st["grid"]}}
+    if not a.no_per_file:
+        gp = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags | ig.FLAG_PER_FILE)
+        gp.load(corpus)
+        for j in range(1, a.n):
+            gp.pass_(j, a.k)
+        t1 = time.perf_counter()
+        gp.pass_(a.n, a.k)
+        t2 = time.perf_counter()
+        same = bool((gp.topk()[0] == g.topk()[0]).all() and (gp.topk()[1] == g.topk()[1]).all())
+        extra["per_file_form"] = {"ms_per_pass": round((t2 - t1) * 1e3, 3),
+                                  "GB_per_s": round(corpus.nbytes / (t2 - t1) / 1e9, 3),
+                                  "scan_ms": round(gp.last_stats()["scan_ms"], 3), "same_table": same}
+        log("per-file form: %.3f ms, same table: %s" % ((t2 - t1) * 1e3, same))
+        gp.close()
+    g.close()
+
+    out = {
+        "metric": "input GB/s per Intergrams pass (n=8,k=1e5) + %HBM roofline; p50/p99 featurize ms",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "binary-like corpus: %d files, lognormal sizes (median 64 KiB, sigma 1.5, cap 16 MiB), "
+                               "%d bytes; one pass n=%d, k_keep=%d, Eq. 2" % (corpus.m, corpus.nbytes, a.n, a.k),
+                   "files": corpus.m, "bytes": corpus.nbytes, "n": a.n, "k_keep": a.k, "freq": "doc"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_scan (scan of pass n=%d)" % a.n, "algo_bytes_per_launch": algo_bytes,
+                     "avg_launch_ms": round(scan_avg, 4)},
+        "extra": extra,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.n, a.k, a.cpu_sample_files, threads)
+        log("cpu baseline: %s" % out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

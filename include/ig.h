@@ -144,6 +144,7 @@ typedef struct {
   uint32_t chunk_syms;   /* launch parameters in use */
   uint32_t block;
   uint32_t grid;
+  uint64_t records;      /* (candidate, sequence) records of sequences split over chunks (Eq. 2) */
 } ig_pass_stats;
 int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
 

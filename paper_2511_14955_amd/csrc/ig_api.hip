@@ -184,7 +184,6 @@ int ig_create(const ig_config *cfg, ig_ctx **out) {
   }
   for (auto &e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete c; return IG_EDEVICE; }
-  if (cfg->symbol_bits == 2) c->lc.chunk_syms = 65536;
   if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->code, 256) ||
       dev_reserve(c, c->sym_of_code, 256)) {
     ig_destroy(c);
@@ -333,6 +332,17 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     nc = c->tkey_slots;
   }
   if (nc >= 0xFFFFFFFFull) return set_error(c, IG_ENOMEM, "candidate space %llu too large", (unsigned long long)nc);
+  if (!occ) {
+    // the pair set holds (sequence, candidate) pairs of sequences split over several chunks
+    uint64_t wmulti = 0;
+    for (uint64_t i = 0; i < c->m; i++) {
+      const uint64_t L = c->h_offs[i + 1] - c->h_offs[i];
+      if (L > c->lc.chunk_syms && L >= n) wmulti += std::min<uint64_t>(L - n + 1, nc);
+    }
+    uint64_t want = 1ull << 22;
+    while (want < wmulti / 2 && want < (1ull << 30)) want <<= 1;
+    if (want > c->pset_slots) c->pset_slots = want;
+  }
 
   ScanParams p{};
   p.data = reinterpret_cast<const uint8_t *>(c->data.p);
@@ -354,6 +364,9 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   }
   p.set_cap = c->lc.set_cap;
   p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
+  if (scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192)
+    return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
+                     (unsigned long long)scan_lds_bytes(p, mode, occ));
   const uint32_t block = c->lc.block;
   const uint32_t grid = (uint32_t)c->n_cu * c->lc.grid_per_cu;
   c->last.chunk_syms = c->lc.chunk_syms;

@@ -47,7 +47,7 @@ template <typename CT> __device__ __forceinline__ void cnt_add(void *cnt, uint32
 __device__ __forceinline__ bool pset_insert(const ScanParams &p, uint32_t file, uint32_t cid) {
   const uint64_t key = ((uint64_t)(file + 1) << 32) | cid;
   uint64_t slot = mix64(key) & p.pmask;
-  for (int probe = 0; probe < 4096; probe++) {
+  for (int probe = 0; probe < 64; probe++) {
     unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(p.pset + slot), 0ull,
                                        (unsigned long long)key);
     if (old == 0ull) return true;
@@ -151,6 +151,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     if (tid == 0) {
       if (p.persistent) s_chunk = atomicAdd(p.qctr, 1u);
       else s_chunk = local_iter == 0 ? p.chunk_base + blockIdx.x : 0xFFFFFFFFu;
+      // a table overflowed: this launch will be replayed with larger tables, stop early
+      if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_chunk = 0xFFFFFFFFu;
       s_over = 0;
     }
     __syncthreads();
