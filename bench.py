@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-file", action="store_true", help="skip the one-launch-per-file comparison")
     ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shape")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the Intergrams pass is measured on a single MI355X; "
@@ -75,6 +76,12 @@ def main():
         st = g.last_stats()
         log("pass %d: %.3f ms (scan %.3f ms, select %.3f ms), kept %d, distinct %d, records %d" % (
             j, st["pass_ms"], st["scan_ms"], st["select_ms"], g.table_info()[1], st["distinct"], st["records"]))
+    tune = None
+    if not a.no_tune:
+        t_t = time.time()
+        tune = g.autotune(a.n, a.k)
+        log("autotune: best %s (%d candidates, identical tables: %s, %.1fs)" % (
+            tune["best"], len(tune["candidates"]), tune["identical"], time.time() - t_t))
     # first pass n (not timed) so that every step can rewind to the n-1 table
     g.pass_(a.n, a.k)
     for _ in range(a.warmup):
@@ -103,9 +110,17 @@ def main():
     extra = {"device_pass_ms": round(sum(pass_ms) / len(pass_ms), 4), "scan_ms": round(scan_avg, 4),
              "select_ms": round(st["select_ms"], 4), "windows": st["windows"], "distinct_counted": st["distinct"],
              "split_file_records": st["records"],
-             "launch": {"chunk_syms": st["chunk_syms"], "block": st["block"], "grid": st["grid"]}}
+             "launch": {"chunk_syms": st["chunk_syms"], "block": st["block"], "grid": st["grid"],
+                        "set_cap": g.launch()["set_cap"]},
+             "graph_captured": not (a.flags & 1)}
+    if tune:
+        extra["autotune"] = {"identical_tables": tune["identical"],
+                             "candidates": [[c["chunk_syms"], c["block"], c["set_cap"], round(c["pass_ms"], 3)]
+                                            for c in tune["candidates"]]}
     if not a.no_per_file:
         gp = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags | ig.FLAG_PER_FILE)
+        lc = g.launch()
+        gp.set_launch(lc["chunk_syms"], lc["block"], lc["set_cap"])
         gp.load(corpus)
         for j in range(1, a.n):
             gp.pass_(j, a.k)

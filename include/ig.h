@@ -151,6 +151,32 @@ int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
 const char *ig_last_error(const ig_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
+ * Launch shape of the scan and its autotuner.
+ *
+ * chunk_syms: symbols per work item (a chunk of one sequence plus its n-1
+ * symbol halo); block: threads per workgroup (256, 512, 1024); set_cap: LDS
+ * de-duplication set entries (power of two).  The shape changes speed only,
+ * never results.
+ *
+ * ig_autotune runs pass n on the loaded corpus for each candidate shape
+ * (rewinding after each), checks that all candidates return the same table,
+ * and keeps the fastest; the chain state is left as it was.  With the
+ * environment variable IG_TUNE_CACHE naming a file, results are read from and
+ * appended to it, keyed by device, corpus shape and (n, k_keep).
+ * --------------------------------------------------------------------------- */
+#define IG_TUNE_MAX 32
+typedef struct {
+  uint32_t n_candidates;
+  struct { uint32_t chunk_syms, block, set_cap; double pass_ms; } cand[IG_TUNE_MAX];  /* pass_ms < 0: shape unusable */
+  uint32_t best;
+  int      identical;     /* 1 if every candidate produced the same table */
+  int      from_cache;
+} ig_tune_report;
+int ig_autotune(ig_ctx *ctx, uint32_t n, uint64_t k_keep, ig_tune_report *rep);
+int ig_get_launch(const ig_ctx *ctx, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap);
+int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set_cap);
+
+/* ---------------------------------------------------------------------------
  * Serving (continuous batching of featurize / count requests).
  *
  * A background thread admits submitted requests while the device memory they

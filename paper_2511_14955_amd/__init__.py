@@ -50,6 +50,19 @@ class ig_pass_stats(ctypes.Structure):
                 ("grid", ctypes.c_uint32), ("records", ctypes.c_uint64)]
 
 
+class _tune_cand(ctypes.Structure):
+    _fields_ = [("chunk_syms", ctypes.c_uint32), ("block", ctypes.c_uint32), ("set_cap", ctypes.c_uint32),
+                ("pass_ms", ctypes.c_double)]
+
+
+IG_TUNE_MAX = 32
+
+
+class ig_tune_report(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_uint32), ("cand", _tune_cand * IG_TUNE_MAX), ("best", ctypes.c_uint32),
+                ("identical", ctypes.c_int), ("from_cache", ctypes.c_int)]
+
+
 class ig_serve_config(ctypes.Structure):
     _fields_ = [("max_inflight_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
                 ("max_batch", ctypes.c_uint32), ("queue_capacity", ctypes.c_uint64)]
@@ -99,6 +112,9 @@ def load_library(path=LIB_PATH):
     lib.ig_last_pass_stats.argtypes = [vp, P(ig_pass_stats)]
     lib.ig_last_error.argtypes = [vp]
     lib.ig_last_error.restype = ctypes.c_char_p
+    lib.ig_autotune.argtypes = [vp, u32, u64, P(ig_tune_report)]
+    lib.ig_get_launch.argtypes = [vp, P(u32), P(u32), P(u32)]
+    lib.ig_set_launch.argtypes = [vp, u32, u32, u32]
     if hasattr(lib, "ig_serve_start"):
         lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
         lib.ig_submit.argtypes = [vp, i32, vp, u64, P(u64), u64, u64, dbl]
@@ -216,6 +232,23 @@ class Intergrams:
                 continue
             self._check(rc)
             return indptr, ind[:nnz.value]
+
+    def autotune(self, n, k_keep):
+        """Search the scan's launch shape on pass n (chain state unchanged); returns a report dict."""
+        rep = ig_tune_report()
+        self._check(self._lib.ig_autotune(self._h, n, k_keep, ctypes.byref(rep)))
+        cands = [{"chunk_syms": c.chunk_syms, "block": c.block, "set_cap": c.set_cap, "pass_ms": c.pass_ms}
+                 for c in rep.cand[:rep.n_candidates]]
+        return {"candidates": cands, "best": cands[rep.best] if cands else None, "identical": bool(rep.identical),
+                "from_cache": bool(rep.from_cache)}
+
+    def launch(self):
+        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(self._lib.ig_get_launch(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"chunk_syms": a.value, "block": b.value, "set_cap": c.value}
+
+    def set_launch(self, chunk_syms, block, set_cap):
+        self._check(self._lib.ig_set_launch(self._h, chunk_syms, block, set_cap))
 
     def last_stats(self):
         st = ig_pass_stats()

@@ -57,6 +57,7 @@ int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
   b.p = p;
   b.bytes = want;
   c->held_bytes += want;
+  c->alloc_gen++;
   return 0;
 }
 
@@ -107,7 +108,8 @@ static uint64_t windows_of(const ig_ctx *c, uint32_t n) {
   return w;
 }
 
-static int upload_chunks(ig_ctx *c) {
+int rebuild_chunks(ig_ctx *c) {
+  c->alloc_gen++;   // captured passes refer to the chunk list
   std::vector<Chunk> ch;
   c->file_chunk0.assign(c->m + 1, 0);
   const uint64_t CH = c->lc.chunk_syms;
@@ -197,6 +199,9 @@ void ig_destroy(ig_ctx *c) {
   if (!c) return;
   serve_teardown(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto &g : c->graphs)
+    for (auto &x : g.exec) (void)hipGraphExecDestroy(x);
+  c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
                     &c->status, &c->cnt, &c->pset, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
@@ -276,7 +281,7 @@ int ig_load_batch(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64
   if (check_hip(c, hipMemcpyAsync(c->code.p, c->h_code, 256, hipMemcpyHostToDevice, s), "code copy") ||
       check_hip(c, hipMemcpyAsync(c->sym_of_code.p, c->h_sym_of_code, 256, hipMemcpyHostToDevice, s), "code copy"))
     return IG_EDEVICE;
-  int rc = upload_chunks(c);
+  int rc = rebuild_chunks(c);
   if (rc) return rc;
   c->loaded = true;
   return IG_OK;
@@ -344,7 +349,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     if (want > c->pset_slots) c->pset_slots = want;
   }
 
-  ScanParams p{};
+  ScanParams p;
+  std::memset(&p, 0, sizeof p);   // padding too: the bytes key captured graphs
   p.data = reinterpret_cast<const uint8_t *>(c->data.p);
   p.offs = reinterpret_cast<const uint64_t *>(c->offs.p);
   p.n = n;
@@ -373,92 +379,167 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   c->last.block = block;
   c->last.grid = grid;
 
+  if (check_hip(c, prepare_scan(b, kw, mode, occ, count64), "scan attributes")) return IG_EDEVICE;
+  const bool per_file = (c->cfg.flags & IG_FLAG_PER_FILE) != 0;
+  const bool use_graph = !per_file && !(c->cfg.flags & IG_FLAG_NO_GRAPH);
   uint32_t replays = 0;
-  float scan_ms = 0.f;
-  if (check_hip(c, hipEventRecord(c->ev[0], s), "event")) return IG_EDEVICE;
+  const uint64_t kmax0 = k_keep;
   for (;;) {
-    if (dev_reserve(c, c->cnt, nc * (count64 ? 8 : 4))) return IG_ENOMEM;
-    p.cnt = c->cnt.p;
-    if (!occ) {
-      if (dev_reserve(c, c->pset, c->pset_slots * 8)) return IG_ENOMEM;
-      p.pset = reinterpret_cast<uint64_t *>(c->pset.p);
-      p.pmask = c->pset_slots - 1;
-    }
+    // every buffer of the pass is reserved before anything is enqueued
     if (mode == MODE_SPARSE) {
       if (dev_reserve(c, c->tkey_lo, c->tkey_slots * 8) || dev_reserve(c, c->tkey_hi, c->tkey_slots * 8) ||
           dev_reserve(c, c->tstate, c->tkey_slots * 4))
         return IG_ENOMEM;
+      nc = c->tkey_slots;
+    }
+    if (dev_reserve(c, c->cnt, nc * (count64 ? 8 : 4))) return IG_ENOMEM;
+    if (!occ && dev_reserve(c, c->pset, c->pset_slots * 8)) return IG_ENOMEM;
+    const uint64_t kmax = std::min<uint64_t>(kmax0, nc);
+    int rc = select_reserve(c, nc, k_keep);
+    if (rc) return rc;
+    TableSet &nt = c->ts[c->nxt];
+    rc = index_reserve(c, nt, n, kmax);
+    if (rc) return rc;
+    p.cnt = c->cnt.p;
+    if (!occ) {
+      p.pset = reinterpret_cast<uint64_t *>(c->pset.p);
+      p.pmask = c->pset_slots - 1;
+    }
+    if (mode == MODE_SPARSE) {
       p.tkey_lo = reinterpret_cast<uint64_t *>(c->tkey_lo.p);
       p.tkey_hi = reinterpret_cast<uint64_t *>(c->tkey_hi.p);
       p.tstate = reinterpret_cast<uint32_t *>(c->tstate.p);
       p.tmask = c->tkey_slots - 1;
-      nc = c->tkey_slots;
     }
-    hipError_t e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
-                           : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
-    if (e == hipSuccess && !occ) e = launch_fill_u64(p.pset, c->pset_slots, 0, s);
-    if (e == hipSuccess && mode == MODE_SPARSE) e = launch_fill_u32(p.tstate, c->tkey_slots, 0, s);
-    if (e == hipSuccess) e = launch_fill_u32(p.status, 16, 0, s);
-    if (e == hipSuccess) e = launch_fill_u32(p.qctr, 16, 0, s);
-    if (check_hip(c, e, "pass fill")) return IG_EDEVICE;
-    if (check_hip(c, hipEventRecord(c->ev[1], s), "event")) return IG_EDEVICE;
-    if (c->cfg.flags & IG_FLAG_PER_FILE) {
-      p.persistent = 0;
-      p.chunks = reinterpret_cast<const Chunk *>(c->chunks_file.p);
-      for (uint64_t f = 0; f < c->m; f++) {
-        const uint32_t c0 = c->file_chunk0[f], c1 = c->file_chunk0[f + 1];
-        if (c1 == c0) continue;
-        p.chunk_base = c0;
-        p.nchunks = c1 - c0;
-        e = launch_scan(p, b, kw, mode, occ, count64, c1 - c0, block, s);
-        if (e != hipSuccess) break;
+    SelectParams sp;
+    std::memset(&sp, 0, sizeof sp);
+    sp.cnt = c->cnt.p;
+    sp.nc = nc;
+    sp.count64 = count64;
+    sp.mode = mode;
+    sp.bits = b;
+    sp.sigma = c->sigma;
+    sp.sym_of_code = reinterpret_cast<const uint8_t *>(c->sym_of_code.p);
+    sp.pk_lo = reinterpret_cast<const uint64_t *>(c->T().lo.p);
+    sp.pk_hi = reinterpret_cast<const uint64_t *>(c->T().hi.p);
+    sp.tk_lo = reinterpret_cast<const uint64_t *>(c->tkey_lo.p);
+    sp.tk_hi = reinterpret_cast<const uint64_t *>(c->tkey_hi.p);
+    const uint32_t sel_count_bits = count64 ? 64 : cbits;
+
+    // the pass in three stages: clear the counters, scan, select and index the new table.
+    // Timing events are recorded between the stages (outside any capture).
+    auto stage = [&](int k) -> hipError_t {
+      hipError_t e = hipSuccess;
+      if (k == 0) {
+        e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
+                    : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
+        if (e == hipSuccess && !occ) e = launch_fill_u64(p.pset, c->pset_slots, 0, s);
+        if (e == hipSuccess && mode == MODE_SPARSE) e = launch_fill_u32(p.tstate, c->tkey_slots, 0, s);
+        if (e == hipSuccess) e = launch_fill_u32(p.status, 16, 0, s);
+        if (e == hipSuccess) e = launch_fill_u32(p.qctr, 16, 0, s);
+      } else if (k == 1) {
+        if (per_file) {
+          p.persistent = 0;
+          p.chunks = reinterpret_cast<const Chunk *>(c->chunks_file.p);
+          for (uint64_t f = 0; f < c->m && e == hipSuccess; f++) {
+            const uint32_t c0 = c->file_chunk0[f], c1 = c->file_chunk0[f + 1];
+            if (c1 == c0) continue;
+            p.chunk_base = c0;
+            p.nchunks = c1 - c0;
+            e = launch_scan(p, b, kw, mode, occ, count64, c1 - c0, block, s);
+          }
+        } else {
+          p.persistent = 1;
+          p.chunks = reinterpret_cast<const Chunk *>(c->chunks_lpt.p);
+          p.chunk_base = 0;
+          p.nchunks = (uint32_t)c->nchunks;
+          if (c->nchunks) e = launch_scan(p, b, kw, mode, occ, count64, grid, block, s);
+        }
+      } else {
+        e = select_enqueue(c, sp, k_keep, n * b, sel_count_bits);
+        if (e == hipSuccess) e = index_enqueue(c, nt, kmax, select_kept_ptr(c));
       }
-    } else {
-      p.persistent = 1;
-      p.chunks = reinterpret_cast<const Chunk *>(c->chunks_lpt.p);
-      p.chunk_base = 0;
-      p.nchunks = (uint32_t)c->nchunks;
-      if (c->nchunks) e = launch_scan(p, b, kw, mode, occ, count64, grid, block, s);
+      return e;
+    };
+
+    hipError_t e = hipSuccess;
+    hipGraphExec_t execs[3] = {nullptr, nullptr, nullptr};
+    if (use_graph) {
+      // a captured stage bakes in every launch argument: key the graphs by their exact bytes
+      if (!per_file) {
+        p.persistent = 1;
+        p.chunks = reinterpret_cast<const Chunk *>(c->chunks_lpt.p);
+        p.chunk_base = 0;
+        p.nchunks = (uint32_t)c->nchunks;
+      }
+      const uint64_t extra[] = {n, k_keep, kmax, nc, (uint64_t)mode, (uint64_t)kw, (uint64_t)occ, (uint64_t)count64,
+                                sel_count_bits, grid, block, c->pset_slots, c->tkey_slots, c->alloc_gen,
+                                nt.map_mask, nt.filt_words, nt.filt_kind,
+                                (uint64_t)(uintptr_t)nt.lo.p, (uint64_t)(uintptr_t)nt.map_val.p, (uint64_t)(uintptr_t)nt.filt.p};
+      std::string key(reinterpret_cast<const char *>(&p), sizeof p);
+      key.append(reinterpret_cast<const char *>(&sp), sizeof sp);
+      key.append(reinterpret_cast<const char *>(extra), sizeof extra);
+      for (auto &g : c->graphs)
+        if (g.key == key) std::copy(g.exec, g.exec + 3, execs);
+      if (!execs[0]) {
+        for (int k = 0; k < 3 && e == hipSuccess; k++) {
+          hipGraph_t graph = nullptr;
+          e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+          if (e == hipSuccess) {
+            hipError_t e1 = stage(k);
+            e = hipStreamEndCapture(s, &graph);
+            if (e1 != hipSuccess) e = e1;
+          }
+          if (e == hipSuccess) e = hipGraphInstantiate(&execs[k], graph, nullptr, nullptr, 0);
+          if (graph) (void)hipGraphDestroy(graph);
+        }
+        if (check_hip(c, e, "pass graph capture")) {
+          for (auto &x : execs)
+            if (x) (void)hipGraphExecDestroy(x);
+          return IG_EDEVICE;
+        }
+        if (c->graphs.size() >= 8) {
+          for (auto &x : c->graphs.front().exec) (void)hipGraphExecDestroy(x);
+          c->graphs.erase(c->graphs.begin());
+        }
+        ig_ctx::GraphEntry ge;
+        ge.key = key;
+        std::copy(execs, execs + 3, ge.exec);
+        c->graphs.push_back(ge);
+      }
     }
-    if (check_hip(c, e, "scan launch")) return IG_EDEVICE;
-    if (check_hip(c, hipEventRecord(c->ev[2], s), "event")) return IG_EDEVICE;
+    for (int k = 0; k < 3 && e == hipSuccess; k++) {
+      e = hipEventRecord(c->ev[k], s);
+      if (e == hipSuccess) e = use_graph ? hipGraphLaunch(execs[k], s) : stage(k);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev[3], s);
+    if (check_hip(c, e, "pass launch")) return IG_EDEVICE;
     uint32_t status = 0;
     if (check_hip(c, hipMemcpyAsync(&status, p.status, 4, hipMemcpyDeviceToHost, s), "status copy") ||
-        check_hip(c, hipStreamSynchronize(s), "scan sync"))
+        check_hip(c, hipStreamSynchronize(s), "pass sync"))
       return IG_EDEVICE;
-    (void)hipEventElapsedTime(&scan_ms, c->ev[1], c->ev[2]);
     if (!status) break;
+    // a table overflowed: grow it and run the pass again (the result does not depend on the sizes)
     if (status & ST_PSET_OVF) c->pset_slots <<= 2;
     if (status & ST_TABLE_OVF) c->tkey_slots <<= 2;
     if (++replays > 8) return set_error(c, IG_ENOMEM, "tables kept overflowing (status %u)", status);
   }
+  uint64_t kept = 0, distinct = 0;
+  int rc = select_read(c, &kept, &distinct);
+  if (rc) return rc;
+  float scan_ms = 0.f, sel_ms = 0.f, total_ms = 0.f;
+  (void)hipEventElapsedTime(&scan_ms, c->ev[1], c->ev[2]);
+  (void)hipEventElapsedTime(&sel_ms, c->ev[2], c->ev[3]);   // selection and index build
+  (void)hipEventElapsedTime(&total_ms, c->ev[0], c->ev[3]);
   c->last.replays = replays;
   c->last.scan_ms = scan_ms;
-
-  // selection
-  SelectParams sp{};
-  sp.cnt = c->cnt.p;
-  sp.nc = nc;
-  sp.count64 = count64;
-  sp.mode = mode;
-  sp.bits = b;
-  sp.sigma = c->sigma;
-  sp.sym_of_code = reinterpret_cast<const uint8_t *>(c->sym_of_code.p);
-  sp.pk_lo = reinterpret_cast<const uint64_t *>(c->T().lo.p);
-  sp.pk_hi = reinterpret_cast<const uint64_t *>(c->T().hi.p);
-  sp.tk_lo = reinterpret_cast<const uint64_t *>(c->tkey_lo.p);
-  sp.tk_hi = reinterpret_cast<const uint64_t *>(c->tkey_hi.p);
-  uint64_t kept = 0;
-  if (check_hip(c, hipEventRecord(c->ev[3], s), "event")) return IG_EDEVICE;
-  int rc = run_select(c, sp, k_keep, n * b, count64 ? 64 : cbits, &kept);
-  if (rc) return rc;
-  float sel_ms = 0.f;
+  c->last.select_ms = sel_ms;
+  c->last.pass_ms = total_ms;
+  c->last.distinct = distinct;
   // commit: the new table (set nxt) becomes current; the old current is kept for ig_rewind
   TableSet &nt = c->ts[c->nxt];
   nt.kept = kept;
   nt.n = n;
-  rc = build_table_index(c, nt);
-  if (rc) return rc;
   {
     const int old_prev = c->prev;
     c->prev = c->cur;
@@ -470,13 +551,6 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   c->kept = kept;
   c->n_prev = n;
   c->fresh = false;
-  if (check_hip(c, hipEventRecord(c->ev[2], s), "event") || check_hip(c, hipStreamSynchronize(s), "pass sync"))
-    return IG_EDEVICE;
-  float total_ms = 0.f;
-  (void)hipEventElapsedTime(&total_ms, c->ev[0], c->ev[2]);
-  (void)hipEventElapsedTime(&sel_ms, c->ev[3], c->ev[2]);
-  c->last.pass_ms = total_ms;
-  c->last.select_ms = sel_ms;
   return IG_OK;
 }
 

@@ -166,11 +166,21 @@ struct ig_ctx {
   ig_pass_stats last{};
   hipEvent_t ev[4]{};
 
+  // captured passes: one executable graph per (pass shape, buffers)
+  struct GraphEntry {
+    std::string key;          // bytes of every argument baked into the captured stages
+    hipGraphExec_t exec[3];   // clear, scan, select + index
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t alloc_gen = 0;     // bumped whenever a device buffer is (re)allocated
+
   // featurize / serving
   void *server = nullptr;
 };
 
 namespace ig {
+// chunk list for the current launch shape (ig_api.hip)
+int rebuild_chunks(ig_ctx *c);
 // serving loop teardown (ig_serve.hip)
 void serve_teardown(ig_ctx *c);
 // allocation helpers (ig_api.hip)
@@ -184,12 +194,17 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ, int count64,
                        uint32_t grid, uint32_t block, hipStream_t s);
+// set the kernel's LDS limit outside of any stream capture
+hipError_t prepare_scan(int bits, int kw, int mode, int occ, int count64);
 size_t scan_lds_bytes(const ScanParams &p, int mode, int occ);
-// selection: returns kept count via *kept (device->host sync inside)
-int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits,
-               uint64_t *kept_out);
-// map + filter over a table set
-int build_table_index(ig_ctx *c, TableSet &t);
+// selection: reserve scratch, enqueue kernels (no host sync), read the kept length afterwards
+int select_reserve(ig_ctx *c, uint64_t nc, uint64_t k_keep);
+hipError_t select_enqueue(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits);
+const unsigned long long *select_kept_ptr(ig_ctx *c);
+int select_read(ig_ctx *c, uint64_t *kept, uint64_t *distinct);
+// map + filter over a table set (sizes bounded by k_max; the length is read on the device)
+int index_reserve(ig_ctx *c, TableSet &t, uint32_t n, uint64_t k_max);
+hipError_t index_enqueue(ig_ctx *c, TableSet &t, uint64_t k_max, const unsigned long long *kept_dev);
 // featurize a device-resident batch into per-file rank bitmaps and CSR
 struct FeatBatch {
   const uint8_t *data;       // device

@@ -255,9 +255,10 @@ template <int B, int KW, int MODE, int OCC, typename CT>
 static hipError_t launch_t(const ScanParams &p, uint32_t grid, uint32_t block, hipStream_t s) {
   const size_t lds = scan_lds_bytes(p, MODE, OCC);
   auto fn = k_scan<B, KW, MODE, OCC, CT>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
+  if (grid == 0) {   // preparation call: allow the whole LDS of a CU (never issued during a capture)
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024 - 4096);
+  }
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, p);
   return hipGetLastError();
 }
@@ -287,6 +288,11 @@ hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ,
   }
   if (mode == MODE_FILTERED) return launch_m<2, 2, MODE_FILTERED>(p, occ, count64, grid, block, s);
   return launch_m<2, 2, MODE_SPARSE>(p, occ, count64, grid, block, s);
+}
+
+hipError_t prepare_scan(int bits, int kw, int mode, int occ, int count64) {
+  ScanParams p{};
+  return launch_scan(p, bits, kw, mode, occ, count64, 0, 0, nullptr);
 }
 
 // ------------------------------------------------------------------ fills (graph-safe, no memset nodes)

@@ -332,14 +332,11 @@ static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap) {
   return (uint32_t)g;
 }
 
-int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits,
-               uint64_t *kept_out) {
-  hipStream_t s = c->stream;
-  const uint64_t K = k_keep < sp.nc ? k_keep : sp.nc;
+int select_reserve(ig_ctx *c, uint64_t nc, uint64_t k_keep) {
+  const uint64_t K = k_keep < nc ? k_keep : nc;
   const uint64_t Kc = K ? K : 1;
-  const uint64_t ncc = sp.nc ? sp.nc : 1;
+  const uint64_t ncc = nc ? nc : 1;
   const uint32_t ntiles = (uint32_t)((Kc + SORT_TILE - 1) / SORT_TILE);
-  // every scratch buffer is reserved before the first launch of the selection
   if (dev_reserve(c, c->selstate, sizeof(SelState)) || dev_reserve(c, c->hist, 512 * 8) ||
       dev_reserve(c, c->sel_cid, Kc * 4) || dev_reserve(c, c->sel_cnt, Kc * 8) ||
       dev_reserve(c, c->sel_klo, 2 * Kc * 8) || dev_reserve(c, c->sel_khi, 2 * Kc * 8) ||
@@ -347,6 +344,29 @@ int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_
       dev_reserve(c, c->thist, (uint64_t)256 * ntiles * 4) || dev_reserve(c, c->ts[c->nxt].lo, Kc * 8) ||
       dev_reserve(c, c->ts[c->nxt].hi, Kc * 8) || dev_reserve(c, c->ts[c->nxt].cnt, Kc * 8))
     return IG_ENOMEM;
+  return IG_OK;
+}
+
+const unsigned long long *select_kept_ptr(ig_ctx *c) {
+  return &reinterpret_cast<const SelState *>(c->selstate.p)->kprime;
+}
+
+int select_read(ig_ctx *c, uint64_t *kept, uint64_t *distinct) {
+  SelState hs;
+  if (check_hip(c, hipMemcpyAsync(&hs, c->selstate.p, sizeof hs, hipMemcpyDeviceToHost, c->stream), "select state copy") ||
+      check_hip(c, hipStreamSynchronize(c->stream), "select sync"))
+    return IG_EDEVICE;
+  *kept = hs.kprime;
+  *distinct = hs.total;
+  return IG_OK;
+}
+
+// Enqueue the selection (no host synchronization; buffers from select_reserve).
+hipError_t select_enqueue(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits) {
+  hipStream_t s = c->stream;
+  const uint64_t K = k_keep < sp.nc ? k_keep : sp.nc;
+  const uint64_t Kc = K ? K : 1;
+  const uint32_t ntiles = (uint32_t)((Kc + SORT_TILE - 1) / SORT_TILE);
   SelState *st = reinterpret_cast<SelState *>(c->selstate.p);
   unsigned long long *hist = reinterpret_cast<unsigned long long *>(c->hist.p);
   uint32_t *sel_cid = reinterpret_cast<uint32_t *>(c->sel_cid.p);
@@ -356,7 +376,8 @@ int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_
   const uint32_t G = (uint32_t)c->n_cu * 4;
 
   hipLaunchKernelGGL(k_sel_reset, dim3(1), dim3(1), 0, s, st);
-  if (launch_fill_u64(reinterpret_cast<uint64_t *>(hist), 512, 0, s) != hipSuccess) return IG_EDEVICE;
+  hipError_t e = launch_fill_u64(reinterpret_cast<uint64_t *>(hist), 512, 0, s);
+  if (e != hipSuccess) return e;
   const uint32_t cl = (count_bits + 7) / 8;
   for (int lev = (int)cl - 1; lev >= 0; lev--) {
     const uint32_t shift = 8u * (uint32_t)lev;
@@ -397,14 +418,7 @@ int run_select(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_
   hipLaunchKernelGGL(k_copy_out, dim3(grid_for(Kc, 256, G)), dim3(256), 0, s, st, alo, ahi, acnt,
                      reinterpret_cast<uint64_t *>(c->ts[c->nxt].lo.p), reinterpret_cast<uint64_t *>(c->ts[c->nxt].hi.p),
                      reinterpret_cast<uint64_t *>(c->ts[c->nxt].cnt.p));
-  if (check_hip(c, hipGetLastError(), "select launch")) return IG_EDEVICE;
-  SelState hs;
-  if (check_hip(c, hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "select state copy") ||
-      check_hip(c, hipStreamSynchronize(s), "select sync"))
-    return IG_EDEVICE;
-  *kept_out = hs.kprime;
-  c->last.distinct = hs.total;
-  return IG_OK;
+  return hipGetLastError();
 }
 
 }  // namespace ig

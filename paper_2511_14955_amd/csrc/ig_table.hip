@@ -22,8 +22,9 @@
 
 namespace ig {
 
-__global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, uint64_t kept, uint64_t *mlo, uint64_t *mhi,
-                             uint32_t *mval, uint64_t mmask) {
+__global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint64_t *mlo,
+                             uint64_t *mhi, uint32_t *mval, uint64_t mmask) {
+  const uint64_t kept = *kept_p;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = tlo[i], hi = thi[i];
     uint64_t slot = hash_key(lo, hi) & mmask;
@@ -38,8 +39,9 @@ __global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, uint64_t 
   }
 }
 
-__global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, uint64_t kept, uint32_t *filt, uint32_t words,
-                               uint32_t kind) {
+__global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *filt,
+                               uint32_t words, uint32_t kind) {
+  const uint64_t kept = *kept_p;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = tlo[i], hi = thi[i];
     if (kind == FILT_DIRECT) {
@@ -52,12 +54,12 @@ __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, uint64_
   }
 }
 
-int build_table_index(ig_ctx *c, TableSet &ts) {
-  hipStream_t s = c->stream;
-  const uint64_t kept = ts.kept;
+// Sizes come from k_max (an upper bound of the table length known on the host);
+// the kernels read the actual length from device memory.
+int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
   uint64_t cap = 1024;
-  while (cap < 2 * kept) cap <<= 1;
-  const uint32_t nbits = ts.n * c->cfg.symbol_bits;
+  while (cap < 2 * k_max) cap <<= 1;
+  const uint32_t nbits = n * c->cfg.symbol_bits;
   const uint64_t maxw = c->lc.filt_max_words;
   uint32_t kind, words;
   if (nbits <= 40 && (1ull << nbits) <= maxw * 32) {
@@ -65,7 +67,7 @@ int build_table_index(ig_ctx *c, TableSet &ts) {
     words = (uint32_t)(((1ull << nbits) + 31) / 32);
   } else {
     kind = FILT_BLOOM;
-    uint64_t w = (kept * 12 + 31) / 32;
+    uint64_t w = (k_max * 12 + 31) / 32;
     if (w < 64) w = 64;
     if (w > maxw) w = maxw;
     words = (uint32_t)w;
@@ -76,20 +78,24 @@ int build_table_index(ig_ctx *c, TableSet &ts) {
   ts.map_mask = cap - 1;
   ts.filt_words = words;
   ts.filt_kind = kind;
-  if (launch_fill_u32(reinterpret_cast<uint32_t *>(ts.map_val.p), cap, 0, s) != hipSuccess ||
-      launch_fill_u32(reinterpret_cast<uint32_t *>(ts.filt.p), words, 0, s) != hipSuccess)
-    return check_hip(c, hipGetLastError(), "index fill") ? IG_EDEVICE : IG_EDEVICE;
-  if (kept) {
-    uint64_t g = (kept + 255) / 256;
-    if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
-                       reinterpret_cast<const uint64_t *>(ts.hi.p), kept, reinterpret_cast<uint64_t *>(ts.map_lo.p),
-                       reinterpret_cast<uint64_t *>(ts.map_hi.p), reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask);
-    hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s,
-                       reinterpret_cast<const uint64_t *>(ts.lo.p), reinterpret_cast<const uint64_t *>(ts.hi.p),
-                       kept, reinterpret_cast<uint32_t *>(ts.filt.p), words, kind);
-  }
-  return check_hip(c, hipGetLastError(), "index build") ? IG_EDEVICE : IG_OK;
+  return IG_OK;
+}
+
+hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned long long *kept_dev) {
+  hipStream_t s = c->stream;
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask + 1, 0, s);
+  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.filt.p), ts.filt_words, 0, s);
+  if (e != hipSuccess) return e;
+  uint64_t g = (k_max + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
+                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint64_t *>(ts.map_lo.p),
+                     reinterpret_cast<uint64_t *>(ts.map_hi.p), reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask);
+  hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
+                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.filt.p),
+                     ts.filt_words, ts.filt_kind);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ featurize
