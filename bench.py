@@ -42,6 +42,56 @@ def cpu_baseline(n, k_keep, sample_files, threads):
                       "%.2f s" % (n, k_keep, sample_files, corpus.nbytes, n - 1, dt)}
 
 
+def serve_stream(g, ig, requests, budget, n_streams, max_batch):
+    """Open-loop replay of the request stream (Poisson arrivals, mean gap 0.5 ms)
+    against the retained table: request i is submitted at its arrival time and
+    its latency runs from that arrival to its row being on the host."""
+    import gen
+    import numpy as np
+    rs = gen.RequestStream()
+    files = [rs.file(i) for i in range(requests)]
+    gaps = np.array([rs.gap(i) for i in range(requests)])
+    nbytes = int(sum(len(f) for f in files))
+    offs = [np.array([0, len(f)], np.uint64) for f in files]
+    g.serve_start(max_inflight_bytes=budget, n_streams=n_streams, max_batch=max_batch, queue_capacity=1 << 20)
+    t0 = g.serve_now() + 0.01
+    arrive = t0 + np.cumsum(gaps)
+    got = {}
+    i = 0
+    late = 0.0
+    while len(got) < requests:
+        now = g.serve_now()
+        while i < requests and arrive[i] <= now:
+            late = max(late, now - arrive[i])
+            rc = g.submit(ig.REQ_FEATURIZE, files[i], offs[i], tag=i, t_arrival=float(arrive[i]))
+            assert rc == ig.IG_OK, rc
+            i += 1
+            now = g.serve_now()
+        for r in g.poll():
+            got[r["tag"]] = r
+        if i < requests and len(got) < requests:
+            wait = arrive[i] - g.serve_now()
+            if wait > 2e-4:
+                time.sleep(wait - 1e-4)
+    t_end = g.serve_now()
+    st = g.serve_stats()
+    g.serve_stop()
+    bad = [t for t, r in got.items() if r["status"] != ig.IG_OK]
+    assert not bad, "requests failed: %s" % bad[:5]
+    lat = np.array([got[t]["t_done"] - got[t]["t_arrival"] for t in range(requests)]) * 1e3
+    span = t_end - t0
+    return {"requests": requests, "bytes": nbytes, "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4), "mean_ms": round(float(lat.mean()), 4),
+            "max_ms": round(float(lat.max()), 4), "offered_per_s": round(requests / float(arrive[-1] - t0), 1),
+            "served_GB_per_s": round(nbytes / span / 1e9, 4), "launches": st["launches"],
+            "peak_running": st["peak_running"], "peak_inflight_bytes": st["peak_inflight_bytes"],
+            "budget_bytes": budget, "n_streams": n_streams, "max_batch": max_batch,
+            "max_submit_lateness_ms": round(late * 1e3, 4),
+            "stream": "Poisson arrivals (mean gap 0.5 ms); each request one binary-like file, lognormal size "
+                      "(median 64 KiB, sigma 1.5, clipped to [4 KiB, 64 MiB]) from the corpus's motif library; "
+                      "table = this pass's n=%d top-k" % g.table_info()[0]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +105,10 @@ def main():
     ap.add_argument("--no-per-file", action="store_true", help="skip the one-launch-per-file comparison")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--serve-requests", type=int, default=4000, help="requests replayed from the stream (0: skip)")
+    ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving HBM budget in bytes")
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=64)
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the Intergrams pass is measured on a single MI355X; "
@@ -117,6 +171,10 @@ def main():
         extra["autotune"] = {"identical_tables": tune["identical"],
                              "candidates": [[c["chunk_syms"], c["block"], c["set_cap"], round(c["pass_ms"], 3)]
                                             for c in tune["candidates"]]}
+    serving = None
+    if a.serve_requests:
+        serving = serve_stream(g, ig, a.serve_requests, a.serve_budget, a.serve_streams, a.serve_batch)
+        log("serving: %s" % serving)
     if not a.no_per_file:
         gp = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags | ig.FLAG_PER_FILE)
         lc = g.launch()
@@ -147,6 +205,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_scan (scan of pass n=%d)" % a.n, "algo_bytes_per_launch": algo_bytes,
                      "avg_launch_ms": round(scan_avg, 4)},
+        "serving": serving,
         "extra": extra,
     }
     if not a.no_cpu:

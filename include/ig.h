@@ -48,7 +48,7 @@ extern "C" {
 #define IG_ETRUNC     (-4)  /* caller buffer too small; the *_out argument holds the size needed */
 #define IG_EOVERFLOW  (-5)  /* 32-bit counts requested but a count could reach 2^32 */
 #define IG_EDEVICE    (-6)  /* HIP runtime error (sticky) */
-#define IG_EBUSY      (-7)  /* serving: queue full, or no serving loop running */
+#define IG_EBUSY      (-7)  /* serving: queue full */
 
 typedef struct ig_ctx ig_ctx;
 
@@ -179,19 +179,29 @@ int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set
 /* ---------------------------------------------------------------------------
  * Serving (continuous batching of featurize / count requests).
  *
- * A background thread admits submitted requests while the device memory they
- * need (input, output and scratch) fits max_inflight_bytes, packs every
- * admitted request into the next launch on one of n_streams streams, and
- * completes them as launches finish.  Requests that arrive while others run
- * are admitted as soon as memory frees; launches on different streams
- * overlap.  The table used is the context's retained table at
- * ig_serve_start; the context must not run passes while serving.
+ * ig_serve_start takes one device arena of max_inflight_bytes (counted
+ * against ig_config.hbm_budget) and starts a background thread.  The thread
+ * admits submitted requests in FIFO order while the device region the next
+ * launch needs (inputs, per-sequence bitmaps, outputs) fits the arena's
+ * largest free block, packs up to max_batch requests into one launch on one
+ * of n_streams streams, and completes them when the launch has finished,
+ * returning the region.  Requests that arrive while launches run are admitted
+ * as soon as a stream and arena space free up; launches on different streams
+ * overlap.  A request that cannot fit even an empty arena completes with
+ * status IG_ENOMEM.  The table served is the context's retained table at
+ * ig_serve_start (the featurization step of Figure 1); ig_pass, ig_rewind,
+ * ig_load_batch, ig_featurize, ig_autotune and ig_set_launch return
+ * IG_ESTATE until ig_serve_stop.  ig_submit, ig_poll and ig_serve_get_stats
+ * may be called from any thread (results go to whoever polls first);
+ * ig_serve_stop and ig_destroy must not overlap them.
  *
- * kind IG_REQ_FEATURIZE: the result is the Boolean row of one sequence
+ * kind IG_REQ_FEATURIZE: one sequence (m = 1); the result is its Boolean row
  *   (int32 ranks, ascending), as ig_featurize.
- * kind IG_REQ_COUNT: the result is, over the request's sequences, the number
- *   of sequences containing each retained gram, as (rank, count) pairs with
- *   rank ascending and count > 0 (Eq. 2 restricted to the table).
+ * kind IG_REQ_COUNT: m >= 1 sequences; the result is, for every retained
+ *   gram found in at least one of them, (rank, number of the request's
+ *   sequences containing it), rank ascending: Eq. 2 restricted to the table.
+ * Errors: IG_ESTATE (no serving loop), IG_EINVAL (bad kind or offsets),
+ *   IG_EBUSY from ig_submit when queue_capacity requests are pending.
  * --------------------------------------------------------------------------- */
 #define IG_REQ_FEATURIZE 0
 #define IG_REQ_COUNT     1
@@ -207,7 +217,7 @@ int ig_serve_start(ig_ctx *ctx, const ig_serve_config *scfg);
 /* Submit one request (a copy of data is taken before returning).
  *  sym_offsets: m+1 offsets of the request's sequences (m = 1 for featurize).
  *  tag: caller id returned with the result.  t_arrival: caller clock (seconds),
- *  returned with the result.  IG_EBUSY when the queue is full. */
+ *  returned with the result.  IG_EBUSY when queue_capacity requests are pending. */
 int ig_submit(ig_ctx *ctx, int kind, const void *data, uint64_t data_bytes,
               const uint64_t *sym_offsets, uint64_t m, uint64_t tag, double t_arrival);
 
@@ -220,9 +230,13 @@ typedef struct {
   uint64_t n;              /* entries in the result */
 } ig_result;
 
-/* Take up to max completed results (oldest first).  For each, up to cap entries are
- * copied to cols[] (and counts[] for COUNT requests, may be NULL otherwise) at
- * offset out_off[i]; out_off has max+1 entries.  *n_out = results taken. */
+/* Take up to max completed results, oldest first, as long as their entries
+ * together fit cap: result i's entries go to cols[out_off[i] .. out_off[i+1])
+ * (ranks) and, for COUNT requests, counts[] at the same positions (counts may
+ * be NULL).  out_off (may be NULL) has max+1 entries.  *n_out = results taken
+ * (0 when none is ready).  If the oldest result alone needs more than cap
+ * entries, nothing is taken, res[0] holds its header (its n is the room
+ * needed) and IG_ETRUNC is returned. */
 int ig_poll(ig_ctx *ctx, ig_result *res, uint64_t max, int32_t *cols, uint64_t *counts,
             uint64_t cap, uint64_t *out_off, uint64_t *n_out);
 /* Library clock in seconds (CLOCK_MONOTONIC). */
@@ -232,8 +246,9 @@ int ig_serve_stop(ig_ctx *ctx);
 
 typedef struct {
   uint64_t submitted, completed, launches, rejected;
-  uint64_t peak_inflight_bytes;
-  uint64_t bytes_in;
+  uint64_t peak_inflight_bytes;   /* most arena bytes held by running launches at once */
+  uint64_t bytes_in;              /* request payload bytes launched */
+  uint64_t peak_running;          /* most launches running at once (<= n_streams) */
 } ig_serve_stats;
 int ig_serve_get_stats(ig_ctx *ctx, ig_serve_stats *st);
 

@@ -75,7 +75,8 @@ class ig_result(ctypes.Structure):
 
 class ig_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("rejected", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64), ("bytes_in", ctypes.c_uint64)]
+                ("rejected", ctypes.c_uint64), ("peak_inflight_bytes", ctypes.c_uint64), ("bytes_in", ctypes.c_uint64),
+                ("peak_running", ctypes.c_uint64)]
 
 
 _lib = None
@@ -115,14 +116,13 @@ def load_library(path=LIB_PATH):
     lib.ig_autotune.argtypes = [vp, u32, u64, P(ig_tune_report)]
     lib.ig_get_launch.argtypes = [vp, P(u32), P(u32), P(u32)]
     lib.ig_set_launch.argtypes = [vp, u32, u32, u32]
-    if hasattr(lib, "ig_serve_start"):
-        lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
-        lib.ig_submit.argtypes = [vp, i32, vp, u64, P(u64), u64, u64, dbl]
-        lib.ig_poll.argtypes = [vp, P(ig_result), u64, vp, vp, u64, P(u64), P(u64)]
-        lib.ig_serve_now.argtypes = []
-        lib.ig_serve_now.restype = dbl
-        lib.ig_serve_stop.argtypes = [vp]
-        lib.ig_serve_get_stats.argtypes = [vp, P(ig_serve_stats)]
+    lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
+    lib.ig_submit.argtypes = [vp, i32, vp, u64, P(u64), u64, u64, dbl]
+    lib.ig_poll.argtypes = [vp, P(ig_result), u64, vp, vp, u64, vp, P(u64)]
+    lib.ig_serve_now.argtypes = []
+    lib.ig_serve_now.restype = dbl
+    lib.ig_serve_stop.argtypes = [vp]
+    lib.ig_serve_get_stats.argtypes = [vp, P(ig_serve_stats)]
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -254,3 +254,58 @@ class Intergrams:
         st = ig_pass_stats()
         self._check(self._lib.ig_last_pass_stats(self._h, ctypes.byref(st)))
         return {f: getattr(st, f) for f, _ in ig_pass_stats._fields_}
+
+    # ------------------------------------------------------------------ serving
+    def serve_start(self, max_inflight_bytes=1 << 30, n_streams=4, max_batch=64, queue_capacity=1 << 16):
+        """Start the continuous-batching loop over the retained table."""
+        cfg = ig_serve_config(max_inflight_bytes, n_streams, max_batch, queue_capacity)
+        self._check(self._lib.ig_serve_start(self._h, ctypes.byref(cfg)))
+
+    def submit(self, kind, data, offsets, tag, t_arrival=None):
+        """Queue one request; returns IG_OK or IG_EBUSY (queue full), raises on bad arguments."""
+        data = np.ascontiguousarray(data, np.uint8)
+        offs = np.ascontiguousarray(offsets, np.uint64)
+        if t_arrival is None:
+            t_arrival = self._lib.ig_serve_now()
+        rc = self._lib.ig_submit(self._h, kind, data.ctypes.data, data.nbytes, _u64p(offs), len(offs) - 1, tag,
+                                 t_arrival)
+        if rc not in (IG_OK, IG_EBUSY):
+            raise IGError(rc, "ig_submit")
+        return rc
+
+    def poll(self, max_results=1024, cap=1 << 20):
+        """Completed results, oldest first: dicts with tag, kind, status, t_arrival, t_done, cols, counts."""
+        res = (ig_result * max(1, max_results))()
+        while True:
+            cols = np.zeros(max(cap, 1), np.int32)
+            counts = np.zeros(max(cap, 1), np.uint64)
+            offs = np.zeros(max_results + 1, np.uint64)
+            nout = ctypes.c_uint64()
+            rc = self._lib.ig_poll(self._h, res, max_results, cols.ctypes.data, counts.ctypes.data, cap,
+                                   offs.ctypes.data, ctypes.byref(nout))
+            if rc == IG_ETRUNC:
+                cap = int(res[0].n)
+                continue
+            if rc:
+                raise IGError(rc, "ig_poll")
+            out = []
+            for i in range(nout.value):
+                r = res[i]
+                a, z = int(offs[i]), int(offs[i + 1])
+                out.append({"tag": r.tag, "kind": r.kind, "status": r.status, "t_arrival": r.t_arrival,
+                            "t_done": r.t_done, "n": r.n, "cols": cols[a:z].copy(),
+                            "counts": counts[a:z].copy() if r.kind == REQ_COUNT else None})
+            return out
+
+    def serve_now(self):
+        """The library clock (seconds) that t_done is measured on."""
+        return self._lib.ig_serve_now()
+
+    def serve_stats(self):
+        st = ig_serve_stats()
+        self._check(self._lib.ig_serve_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ig_serve_stats._fields_}
+
+    def serve_stop(self):
+        """Drain in-flight work and stop the loop (results not yet polled are dropped)."""
+        self._check(self._lib.ig_serve_stop(self._h))

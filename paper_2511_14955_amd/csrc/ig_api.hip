@@ -594,6 +594,7 @@ int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_
                  uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
   if (!c) return IG_EINVAL;
   if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
   if (c->fresh || !c->loaded) return set_error(c, IG_ESTATE, "no pass has run");
   if (!sym_offsets || sym_offsets[0] != 0 || !indptr) return set_error(c, IG_EINVAL, "bad offsets");
   for (uint64_t i = 0; i < m; i++)

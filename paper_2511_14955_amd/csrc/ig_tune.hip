@@ -59,6 +59,7 @@ static void cache_store(const std::string &key, const LaunchCfg &lc) {
 extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_report *rep) {
   if (!c) return IG_EINVAL;
   if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
   if (!c->loaded) return set_error(c, IG_ESTATE, "no corpus loaded");
   if (rep) std::memset(rep, 0, sizeof *rep);
   const std::string key = tune_key(c, n, k_keep);
@@ -179,6 +180,7 @@ extern "C" int ig_get_launch(const ig_ctx *c, uint32_t *chunk_syms, uint32_t *bl
 
 extern "C" int ig_set_launch(ig_ctx *c, uint32_t chunk_syms, uint32_t block, uint32_t set_cap) {
   if (!c) return IG_EINVAL;
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
   if (chunk_syms < 1024 || chunk_syms > 65536 || (block != 256 && block != 512 && block != 1024) || set_cap < 1024 ||
       set_cap > 32768 || (set_cap & (set_cap - 1)))
     return set_error(c, IG_EINVAL, "bad launch shape");
