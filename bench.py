@@ -25,6 +25,33 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def scan_sources_digest():
+    """SHA-256 over the scan kernel's sources, to tie counter records to the code they measured."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ig_scan.hip", "ig_internal.h"):
+        with open(os.path.join(ROOT, "paper_2511_14955_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(n, launch):
+    """HBM bytes per scan launch from the committed PMC record for this kernel source and launch
+    shape (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), else None."""
+    import glob
+    import re
+    dig = scan_sources_digest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as fh:
+            text = fh.read()
+        for block in re.findall(r"```json\n(.*?)\n```", text, flags=re.S):
+            rec = json.loads(block)
+            if (rec.get("kernel") == "k_scan" and rec.get("n") == n and rec.get("scan_sources_sha256") == dig
+                    and list(rec.get("launch", [])) == list(launch)):
+                return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 def cpu_baseline(n, k_keep, sample_files, threads):
     """The CPU oracle as it stands, on the first sample_files files of the same corpus."""
     import gen
@@ -105,6 +132,9 @@ def main():
     ap.add_argument("--no-per-file", action="store_true", help="skip the one-launch-per-file comparison")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shape")
+    ap.add_argument("--launch", default=None, help="fixed scan launch shape CHUNK,BLOCK,SETCAP (no autotune)")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
+                    help="only stream BYTES through a plain device copy kernel 5 times (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests replayed from the stream (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving HBM budget in bytes")
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -114,6 +144,18 @@ def main():
         print("bench.py runs on one GPU only: the Intergrams pass is measured on a single MI355X; "
               "--gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if a.copy_calibrate:
+        # a plain streaming kernel of known size: reads BYTES and writes BYTES
+        import torch
+        n = a.copy_calibrate // 4
+        src = torch.arange(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibrate_bytes": n * 4, "launches": 5, "kernel": "torch.neg int32"}), flush=True)
+        return
 
     import gen
     import paper_2511_14955_amd as ig
@@ -125,13 +167,15 @@ def main():
 
     g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags)
     g.load(corpus)
+    if a.launch:
+        g.set_launch(*[int(x) for x in a.launch.split(",")])
     for j in range(1, a.n):
         g.pass_(j, a.k)
         st = g.last_stats()
         log("pass %d: %.3f ms (scan %.3f ms, select %.3f ms), kept %d, distinct %d, records %d" % (
             j, st["pass_ms"], st["scan_ms"], st["select_ms"], g.table_info()[1], st["distinct"], st["records"]))
     tune = None
-    if not a.no_tune:
+    if not a.no_tune and not a.launch:
         t_t = time.time()
         tune = g.autotune(a.n, a.k)
         log("autotune: best %s (%d candidates, identical tables: %s, %.1fs)" % (
@@ -191,6 +235,7 @@ def main():
                                   "scan_ms": round(gp.last_stats()["scan_ms"], 3), "same_table": same}
         log("per-file form: %.3f ms, same table: %s" % ((t2 - t1) * 1e3, same))
         gp.close()
+    g_launch = g.launch()
     g.close()
 
     out = {
@@ -208,6 +253,10 @@ def main():
         "serving": serving,
         "extra": extra,
     }
+    lc = g_launch
+    traffic, tsrc = profiled_traffic(a.n, [lc["chunk_syms"], lc["block"], lc["set_cap"]])
+    out["roofline"]["traffic"] = traffic
+    out["roofline"]["traffic_source"] = tsrc
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.n, a.k, a.cpu_sample_files, threads)
         log("cpu baseline: %s" % out["cpu_baseline"])
