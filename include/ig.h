@@ -134,9 +134,9 @@ int  ig_featurize(ig_ctx *ctx, const void *data, uint64_t data_bytes,
  * the scan kernel (milliseconds, hipEvent-timed on the context's stream), windows
  * scanned, distinct grams counted, and the scan kernel's average duration. */
 typedef struct {
-  double   pass_ms;
-  double   scan_ms;
-  double   select_ms;
+  double   pass_ms;      /* whole pass: clear, scan, counting, selection, index */
+  double   scan_ms;      /* the scan kernel */
+  double   select_ms;    /* selection and index build */
   uint64_t windows;
   uint64_t distinct;
   uint64_t input_bytes;
@@ -144,7 +144,8 @@ typedef struct {
   uint32_t chunk_syms;   /* launch parameters in use */
   uint32_t block;
   uint32_t grid;
-  uint64_t records;      /* (candidate, sequence) records of sequences split over chunks (Eq. 2) */
+  uint64_t records;      /* Eq. 2: chunk-distinct (candidate, sequence) records counted once per sequence */
+  double   dedup_ms;     /* Eq. 2: counting the records once per sequence */
 } ig_pass_stats;
 int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
 

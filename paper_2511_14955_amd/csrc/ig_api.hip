@@ -122,6 +122,7 @@ int rebuild_chunks(ig_ctx *c) {
       k.file = (uint32_t)f;
       k.nsym = (uint32_t)std::min<uint64_t>(CH, L - s);
       k.multi = L > CH ? 1u : 0u;
+      k.fci = (uint32_t)ch.size();
       ch.push_back(k);
     }
   }
@@ -200,10 +201,11 @@ void ig_destroy(ig_ctx *c) {
   serve_teardown(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto &g : c->graphs)
-    for (auto &x : g.exec) (void)hipGraphExecDestroy(x);
+    for (auto &x : g.exec)
+      if (x) (void)hipGraphExecDestroy(x);
   c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
-                    &c->status, &c->cnt, &c->pset, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
+                    &c->status, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
@@ -337,17 +339,6 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     nc = c->tkey_slots;
   }
   if (nc >= 0xFFFFFFFFull) return set_error(c, IG_ENOMEM, "candidate space %llu too large", (unsigned long long)nc);
-  if (!occ) {
-    // the pair set holds (sequence, candidate) pairs of sequences split over several chunks
-    uint64_t wmulti = 0;
-    for (uint64_t i = 0; i < c->m; i++) {
-      const uint64_t L = c->h_offs[i + 1] - c->h_offs[i];
-      if (L > c->lc.chunk_syms && L >= n) wmulti += std::min<uint64_t>(L - n + 1, nc);
-    }
-    uint64_t want = 1ull << 22;
-    while (want < wmulti / 2 && want < (1ull << 30)) want <<= 1;
-    if (want > c->pset_slots) c->pset_slots = want;
-  }
 
   ScanParams p;
   std::memset(&p, 0, sizeof p);   // padding too: the bytes key captured graphs
@@ -380,6 +371,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   c->last.grid = grid;
 
   if (check_hip(c, prepare_scan(b, kw, mode, occ, count64), "scan attributes")) return IG_EDEVICE;
+  const uint64_t T = dedup_tile();
+  const uint32_t nct = (uint32_t)c->nchunks;
   const bool per_file = (c->cfg.flags & IG_FLAG_PER_FILE) != 0;
   const bool use_graph = !per_file && !(c->cfg.flags & IG_FLAG_NO_GRAPH);
   uint32_t replays = 0;
@@ -393,7 +386,62 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       nc = c->tkey_slots;
     }
     if (dev_reserve(c, c->cnt, nc * (count64 ? 8 : 4))) return IG_ENOMEM;
-    if (!occ && dev_reserve(c, c->pset, c->pset_slots * 8)) return IG_ENOMEM;
+    // Eq. 2: records of every chunk, bucketed and counted once per sequence
+    DedupShape sh{};
+    DedupParams dp;
+    std::memset(&dp, 0, sizeof dp);
+    if (!occ) {
+      sh = dedup_shape(nc, c->m);
+      const uint64_t floor_cap = ((uint64_t)sh.nb1 + 1) * T;
+      if (c->rec_cap < floor_cap) {
+        const uint64_t guess = std::min<uint64_t>(std::max<uint64_t>(W, 1), std::max<uint64_t>(1ull << 22, W / 4));
+        c->rec_cap = (guess + floor_cap + T - 1) / T * T;
+      }
+      const uint64_t cap = c->rec_cap, ntmax = cap / T;
+      const uint64_t n1 = (uint64_t)sh.nb1 * nct, n2 = ntmax * sh.nb2;
+      const uint64_t tmp = std::max(dedup_scan_tmp_entries(n1), dedup_scan_tmp_entries(n2));
+      if (dev_reserve(c, c->rec0, (c->total_syms + 16) * 4) || dev_reserve(c, c->nrec, std::max<uint64_t>(nct, 1) * 4) ||
+          dev_reserve(c, c->hist1, std::max<uint64_t>(n1, 1) * 4) || dev_reserve(c, c->g1, (n1 + 1) * 8) ||
+          dev_reserve(c, c->scan_tmp, tmp * 8) || dev_reserve(c, c->base1, ((uint64_t)sh.nb1 + 1) * 8) ||
+          dev_reserve(c, c->bend, (uint64_t)sh.nb1 * 8) || dev_reserve(c, c->dscal, 64) ||
+          dev_reserve(c, c->l1, cap * sh.w1) || dev_reserve(c, c->l2, cap * sh.w2) ||
+          dev_reserve(c, c->hist2, n2 * 4) || dev_reserve(c, c->g2, (n2 + 1) * 8) ||
+          dev_reserve(c, c->fin, ((uint64_t)sh.nb1 * sh.nb2 + 1) * 8))
+        return IG_ENOMEM;
+      dp.chunks = reinterpret_cast<const Chunk *>(c->chunks_file.p);
+      dp.nct = nct;
+      dp.nb1 = sh.nb1;
+      dp.nb2 = sh.nb2;
+      dp.low1 = sh.low1;
+      dp.low2 = sh.low2;
+      dp.w1 = sh.w1;
+      dp.w2 = sh.w2;
+      dp.rec0 = reinterpret_cast<const uint32_t *>(c->rec0.p);
+      dp.nrec = reinterpret_cast<const uint32_t *>(c->nrec.p);
+      dp.hist1 = reinterpret_cast<const uint32_t *>(c->hist1.p);
+      dp.g1 = reinterpret_cast<uint64_t *>(c->g1.p);
+      dp.scan_tmp = reinterpret_cast<uint64_t *>(c->scan_tmp.p);
+      dp.base1 = reinterpret_cast<uint64_t *>(c->base1.p);
+      dp.bend = reinterpret_cast<uint64_t *>(c->bend.p);
+      dp.dscal = reinterpret_cast<uint64_t *>(c->dscal.p);
+      dp.l1 = c->l1.p;
+      dp.l2 = c->l2.p;
+      dp.cap = cap;
+      dp.ntmax = ntmax;
+      dp.hist2 = reinterpret_cast<uint32_t *>(c->hist2.p);
+      dp.g2 = reinterpret_cast<uint64_t *>(c->g2.p);
+      dp.fin = reinterpret_cast<uint64_t *>(c->fin.p);
+      dp.cnt = c->cnt.p;
+      dp.nc = nc;
+      dp.status = reinterpret_cast<uint32_t *>(c->status.p);
+      p.rec = reinterpret_cast<uint32_t *>(c->rec0.p);
+      p.nrec = reinterpret_cast<uint32_t *>(c->nrec.p);
+      p.hist1 = reinterpret_cast<uint32_t *>(c->hist1.p);
+      p.nct = nct;
+      p.low1 = sh.low1;
+      p.nb1 = sh.nb1;
+      if (check_hip(c, prepare_dedup(sh.low2), "counting attributes")) return IG_EDEVICE;
+    }
     const uint64_t kmax = std::min<uint64_t>(kmax0, nc);
     int rc = select_reserve(c, nc, k_keep);
     if (rc) return rc;
@@ -401,10 +449,6 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     rc = index_reserve(c, nt, n, kmax);
     if (rc) return rc;
     p.cnt = c->cnt.p;
-    if (!occ) {
-      p.pset = reinterpret_cast<uint64_t *>(c->pset.p);
-      p.pmask = c->pset_slots - 1;
-    }
     if (mode == MODE_SPARSE) {
       p.tkey_lo = reinterpret_cast<uint64_t *>(c->tkey_lo.p);
       p.tkey_hi = reinterpret_cast<uint64_t *>(c->tkey_hi.p);
@@ -426,14 +470,15 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     sp.tk_hi = reinterpret_cast<const uint64_t *>(c->tkey_hi.p);
     const uint32_t sel_count_bits = count64 ? 64 : cbits;
 
-    // the pass in three stages: clear the counters, scan, select and index the new table.
-    // Timing events are recorded between the stages (outside any capture).
+    // the pass in four stages: clear, scan, count once per sequence (Eq. 2), select and
+    // index the new table.  Timing events are recorded between the stages (outside any capture).
     auto stage = [&](int k) -> hipError_t {
       hipError_t e = hipSuccess;
       if (k == 0) {
-        e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
-                    : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
-        if (e == hipSuccess && !occ) e = launch_fill_u64(p.pset, c->pset_slots, 0, s);
+        // Eq. 2 counts are written whole by the counting stage; Eq. 1 adds into zeroed counters
+        if (occ)
+          e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
+                      : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
         if (e == hipSuccess && mode == MODE_SPARSE) e = launch_fill_u32(p.tstate, c->tkey_slots, 0, s);
         if (e == hipSuccess) e = launch_fill_u32(p.status, 16, 0, s);
         if (e == hipSuccess) e = launch_fill_u32(p.qctr, 16, 0, s);
@@ -455,15 +500,18 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
           p.nchunks = (uint32_t)c->nchunks;
           if (c->nchunks) e = launch_scan(p, b, kw, mode, occ, count64, grid, block, s);
         }
+      } else if (k == 2) {
+        if (!occ) e = dedup_enqueue(dp, c->n_cu, s);
       } else {
         e = select_enqueue(c, sp, k_keep, n * b, sel_count_bits);
         if (e == hipSuccess) e = index_enqueue(c, nt, kmax, select_kept_ptr(c));
       }
       return e;
     };
+    const int NST = 4;
 
     hipError_t e = hipSuccess;
-    hipGraphExec_t execs[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t execs[4] = {nullptr, nullptr, nullptr, nullptr};
     if (use_graph) {
       // a captured stage bakes in every launch argument: key the graphs by their exact bytes
       if (!per_file) {
@@ -473,16 +521,18 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
         p.nchunks = (uint32_t)c->nchunks;
       }
       const uint64_t extra[] = {n, k_keep, kmax, nc, (uint64_t)mode, (uint64_t)kw, (uint64_t)occ, (uint64_t)count64,
-                                sel_count_bits, grid, block, c->pset_slots, c->tkey_slots, c->alloc_gen,
+                                sel_count_bits, grid, block, c->rec_cap, c->tkey_slots, c->alloc_gen,
                                 nt.map_mask, nt.filt_words, nt.filt_kind,
                                 (uint64_t)(uintptr_t)nt.lo.p, (uint64_t)(uintptr_t)nt.map_val.p, (uint64_t)(uintptr_t)nt.filt.p};
       std::string key(reinterpret_cast<const char *>(&p), sizeof p);
       key.append(reinterpret_cast<const char *>(&sp), sizeof sp);
+      key.append(reinterpret_cast<const char *>(&dp), sizeof dp);
       key.append(reinterpret_cast<const char *>(extra), sizeof extra);
       for (auto &g : c->graphs)
-        if (g.key == key) std::copy(g.exec, g.exec + 3, execs);
+        if (g.key == key) std::copy(g.exec, g.exec + NST, execs);
       if (!execs[0]) {
-        for (int k = 0; k < 3 && e == hipSuccess; k++) {
+        for (int k = 0; k < NST && e == hipSuccess; k++) {
+          if (k == 2 && occ) continue;   // no counting stage for Eq. 1
           hipGraph_t graph = nullptr;
           e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
           if (e == hipSuccess) {
@@ -499,40 +549,49 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
           return IG_EDEVICE;
         }
         if (c->graphs.size() >= 8) {
-          for (auto &x : c->graphs.front().exec) (void)hipGraphExecDestroy(x);
+          for (auto &x : c->graphs.front().exec)
+            if (x) (void)hipGraphExecDestroy(x);
           c->graphs.erase(c->graphs.begin());
         }
         ig_ctx::GraphEntry ge;
         ge.key = key;
-        std::copy(execs, execs + 3, ge.exec);
+        std::copy(execs, execs + NST, ge.exec);
         c->graphs.push_back(ge);
       }
     }
-    for (int k = 0; k < 3 && e == hipSuccess; k++) {
+    for (int k = 0; k < NST && e == hipSuccess; k++) {
       e = hipEventRecord(c->ev[k], s);
-      if (e == hipSuccess) e = use_graph ? hipGraphLaunch(execs[k], s) : stage(k);
+      if (e == hipSuccess && !(k == 2 && occ)) e = use_graph ? hipGraphLaunch(execs[k], s) : stage(k);
     }
-    if (e == hipSuccess) e = hipEventRecord(c->ev[3], s);
+    if (e == hipSuccess) e = hipEventRecord(c->ev[NST], s);
     if (check_hip(c, e, "pass launch")) return IG_EDEVICE;
     uint32_t status = 0;
+    uint64_t dsc[3] = {0, 0, 0};
     if (check_hip(c, hipMemcpyAsync(&status, p.status, 4, hipMemcpyDeviceToHost, s), "status copy") ||
+        (!occ && check_hip(c, hipMemcpyAsync(dsc, c->dscal.p, sizeof dsc, hipMemcpyDeviceToHost, s), "record count copy")) ||
         check_hip(c, hipStreamSynchronize(s), "pass sync"))
       return IG_EDEVICE;
+    c->last.records = dsc[0];
     if (!status) break;
     // a table overflowed: grow it and run the pass again (the result does not depend on the sizes)
-    if (status & ST_PSET_OVF) c->pset_slots <<= 2;
     if (status & ST_TABLE_OVF) c->tkey_slots <<= 2;
+    if (status == ST_REC_OVF) {   // (after a table overflow the record totals are stale)
+      const uint64_t need = dsc[2] + ((uint64_t)sh.nb1 + 1) * T;
+      c->rec_cap = std::max<uint64_t>(c->rec_cap * 2, (need + T - 1) / T * T);
+    }
     if (++replays > 8) return set_error(c, IG_ENOMEM, "tables kept overflowing (status %u)", status);
   }
   uint64_t kept = 0, distinct = 0;
   int rc = select_read(c, &kept, &distinct);
   if (rc) return rc;
-  float scan_ms = 0.f, sel_ms = 0.f, total_ms = 0.f;
+  float scan_ms = 0.f, dd_ms = 0.f, sel_ms = 0.f, total_ms = 0.f;
   (void)hipEventElapsedTime(&scan_ms, c->ev[1], c->ev[2]);
-  (void)hipEventElapsedTime(&sel_ms, c->ev[2], c->ev[3]);   // selection and index build
-  (void)hipEventElapsedTime(&total_ms, c->ev[0], c->ev[3]);
+  (void)hipEventElapsedTime(&dd_ms, c->ev[2], c->ev[3]);    // once-per-sequence counting
+  (void)hipEventElapsedTime(&sel_ms, c->ev[3], c->ev[4]);   // selection and index build
+  (void)hipEventElapsedTime(&total_ms, c->ev[0], c->ev[4]);
   c->last.replays = replays;
   c->last.scan_ms = scan_ms;
+  c->last.dedup_ms = dd_ms;
   c->last.select_ms = sel_ms;
   c->last.pass_ms = total_ms;
   c->last.distinct = distinct;

@@ -49,12 +49,12 @@ struct Chunk {
   uint32_t file;
   uint32_t nsym;    // symbols owned (windows start in [s0, s0 + nsym))
   uint32_t multi;   // the file has more than one chunk
-  uint32_t pad;
+  uint32_t fci;     // index of this chunk in file order (records and histograms are kept in that order)
 };
 
 enum PassMode { MODE_DENSE = 0, MODE_FILTERED = 1, MODE_SPARSE = 2 };
 enum FilterKind { FILT_NONE = 0, FILT_DIRECT = 1, FILT_BLOOM = 2 };
-enum StatusBits { ST_PSET_OVF = 1u, ST_TABLE_OVF = 2u };
+enum StatusBits { ST_TABLE_OVF = 2u, ST_REC_OVF = 4u };
 
 static constexpr uint32_t LDS_EMPTY = 0xFFFFFFFFu;
 
@@ -82,14 +82,53 @@ struct ScanParams {
   uint64_t *tkey_lo, *tkey_hi;
   uint32_t *tstate;
   uint64_t tmask;
-  // counts and cross-chunk de-duplication
+  // counts (Eq. 1), or chunk-distinct records for once-per-sequence counting (Eq. 2)
   void *cnt;
-  uint64_t *pset;
-  uint64_t pmask;
+  uint32_t *rec;                 // Eq. 2: one u32 slot per symbol; a chunk writes its records at [s0, s0 + nrec)
+  uint32_t *nrec;                // Eq. 2: records per chunk (file-order index)
+  uint32_t *hist1;               // Eq. 2: [bucket][chunk] counts of the records' top bits
+  uint32_t nct;                  // chunks in file order (histogram row length)
+  uint32_t low1;                 // level-1 bucket = cid >> low1
+  uint32_t nb1;                  // level-1 buckets (<= 256)
   uint32_t *status;
   uint32_t set_cap;              // LDS de-duplication set entries (power of two)
   uint32_t stage_bytes;          // LDS staging bytes
 };
+
+// Once-per-sequence counting from chunk records (see ig_dedup.hip).
+struct DedupShape {
+  uint32_t nb1, nb2;             // level-1 and level-2 bucket counts (powers of two)
+  uint32_t low1, low2;           // candidate bits below the level-1 / final bucket
+  uint32_t w1, w2;               // record bytes at level 1 / level 2 (4 or 8)
+};
+struct DedupParams {
+  const Chunk *chunks;           // file order
+  uint32_t nct;
+  uint32_t nb1, nb2, low1, low2, w1, w2;
+  const uint32_t *rec0;          // the scan's slab
+  const uint32_t *nrec;
+  const uint32_t *hist1;         // [nb1][nct]
+  uint64_t *g1;                  // scan of hist1 (nb1*nct + 1)
+  uint64_t *scan_tmp;
+  uint64_t *base1;               // nb1 + 1 tile-aligned bucket starts
+  uint64_t *bend;                // nb1 bucket ends
+  uint64_t *dscal;               // [0] records, [1] tiles, [2] padded records
+  void *l1;
+  void *l2;
+  uint64_t cap;                  // capacity of l1 and l2 (records, multiple of the tile)
+  uint64_t ntmax;                // tile slots (cap / tile)
+  uint32_t *hist2;               // ntmax * nb2
+  uint64_t *g2;                  // scan of hist2 (ntmax*nb2 + 1)
+  uint64_t *fin;                 // nb1*nb2 + 1 final bucket starts in l2
+  void *cnt;                     // u32 counts, nc entries
+  uint64_t nc;
+  uint32_t *status;
+};
+DedupShape dedup_shape(uint64_t nc, uint64_t m);
+uint64_t dedup_tile();
+uint64_t dedup_scan_tmp_entries(uint64_t n);
+hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s);
+hipError_t prepare_dedup(uint32_t low2);
 
 // Parameters of the selection of the k_keep best candidates.
 struct SelectParams {
@@ -159,17 +198,20 @@ struct ig_ctx {
   ig::TableSet &T() { return ts[cur]; }
 
   // pass scratch
-  ig::DevBuf cnt, pset, tkey_lo, tkey_hi, tstate;
-  uint64_t pset_slots = 1ull << 22, tkey_slots = 0;
+  ig::DevBuf cnt, tkey_lo, tkey_hi, tstate;
+  uint64_t tkey_slots = 0;
+  // once-per-sequence counting: slab, per-chunk counts and histograms, bucketed records
+  ig::DevBuf rec0, nrec, hist1, g1, scan_tmp, base1, bend, dscal, l1, l2, hist2, g2, fin;
+  uint64_t rec_cap = 0;         // records the bucketed arrays hold (multiple of the tile)
   ig::DevBuf sel_cid, sel_cnt, sel_klo, sel_khi, tie_a, tie_b, sort_tmp, hist, selstate, thist;
 
   ig_pass_stats last{};
-  hipEvent_t ev[4]{};
+  hipEvent_t ev[5]{};
 
   // captured passes: one executable graph per (pass shape, buffers)
   struct GraphEntry {
     std::string key;          // bytes of every argument baked into the captured stages
-    hipGraphExec_t exec[3];   // clear, scan, select + index
+    hipGraphExec_t exec[4];   // clear, scan, once-per-sequence counting, select + index
   };
   std::vector<GraphEntry> graphs;
   uint64_t alloc_gen = 0;     // bumped whenever a device buffer is (re)allocated

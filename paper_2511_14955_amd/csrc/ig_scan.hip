@@ -11,10 +11,13 @@
 // The prefix test first consults a compact filter image held in LDS (a direct
 // bitmap when the prefix space is small, otherwise a blocked Bloom filter with
 // no false negatives); only filter hits probe the exact key -> rank map.
-// Survivors become dense candidate ids.  Per-sequence de-duplication (Eq. 2)
-// uses an LDS hash set per chunk; sequences split over several chunks (or a
-// chunk whose set overflowed) go through a device-wide set of
-// (sequence, candidate) pairs so that each pair is counted once.
+// Survivors become dense candidate ids, de-duplicated per chunk in an LDS hash
+// set.  For Eq. 1 the set also holds per-candidate counts that are added to the
+// count array at the end of the chunk.  For Eq. 2 the chunk writes its distinct
+// candidates ("records") into its own slot range of a slab, with a histogram of
+// their top bits; the records are counted once per sequence afterwards without
+// device-scope atomics (ig_dedup.hip).  A candidate that finds the LDS set full
+// is recorded directly (a duplicate record within one sequence is harmless).
 #include "ig_internal.h"
 
 namespace ig {
@@ -41,21 +44,6 @@ template <> struct KeyT<2> {
 
 template <typename CT> __device__ __forceinline__ void cnt_add(void *cnt, uint32_t cid, CT v) {
   __hip_atomic_fetch_add(reinterpret_cast<CT *>(cnt) + cid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Device-wide set of (sequence, candidate) pairs: true if the pair is new.
-__device__ __forceinline__ bool pset_insert(const ScanParams &p, uint32_t file, uint32_t cid) {
-  const uint64_t key = ((uint64_t)(file + 1) << 32) | cid;
-  uint64_t slot = mix64(key) & p.pmask;
-  for (int probe = 0; probe < 64; probe++) {
-    unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(p.pset + slot), 0ull,
-                                       (unsigned long long)key);
-    if (old == 0ull) return true;
-    if (old == key) return false;
-    slot = (slot + 1) & p.pmask;
-  }
-  atomicOr(p.status, ST_PSET_OVF);
-  return false;
 }
 
 // Exact lookup in the key -> rank+1 map (capacity >= 2x entries, so a probe run ends).
@@ -122,12 +110,14 @@ __device__ __forceinline__ uint32_t stage_sym(const uint8_t *s_stage, uint64_t g
 template <int B, int KW, int MODE, int OCC, typename CT>
 __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   extern __shared__ __align__(16) uint8_t lds[];
+  __shared__ uint32_t s_h1[256];       // Eq. 2: histogram of this chunk's records (level-1 buckets)
+  __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
   uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? p.filt_words : 0);
   uint32_t *s_cnt = s_set + p.set_cap;                 // OCC only
   uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
-  __shared__ uint32_t s_chunk, s_over;
+  __shared__ uint32_t s_chunk;
 
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
   const uint32_t n = p.n;
@@ -143,8 +133,18 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     s_set[i] = LDS_EMPTY;
     if (OCC) s_cnt[i] = 0;
   }
-  for (uint32_t i = tid; i < 256; i += bs) s_code[i] = p.code[i];
+  for (uint32_t i = tid; i < 256; i += bs) {
+    s_code[i] = p.code[i];
+    s_h1[i] = 0;
+  }
+  if (tid == 0) s_nrec = 0;
   __syncthreads();
+  // Eq. 2: append one record of this chunk (slot c.s0 + k, k < windows of the chunk)
+  auto emit = [&](uint64_t s0, uint32_t cid) {
+    const uint32_t k = atomicAdd(&s_nrec, 1u);
+    p.rec[s0 + k] = cid;
+    atomicAdd(s_h1 + (p.low1 >= 32 ? 0u : (cid >> p.low1)), 1u);
+  };
 
   uint32_t local_iter = 0;
   for (;;) {
@@ -153,7 +153,6 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       else s_chunk = local_iter == 0 ? p.chunk_base + blockIdx.x : 0xFFFFFFFFu;
       // a table overflowed: this launch will be replayed with larger tables, stop early
       if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_chunk = 0xFFFFFFFFu;
-      s_over = 0;
     }
     __syncthreads();
     const uint32_t ci = s_chunk;
@@ -166,7 +165,15 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     uint64_t wend = c.s0 + c.nsym;
     if (flen < n) wend = wbeg;
     else if (wend > fend - n + 1) wend = fend - n + 1;
-    if (wbeg >= wend) { __syncthreads(); continue; }
+    if (wbeg >= wend) {
+      // no window: an Eq. 2 chunk still reports zero records
+      if (!OCC) {
+        if (tid == 0) p.nrec[c.fci] = 0;
+        for (uint32_t b = tid; b < p.nb1; b += bs) p.hist1[(uint64_t)b * p.nct + c.fci] = 0;
+      }
+      __syncthreads();
+      continue;
+    }
     const uint64_t nwin = wend - wbeg;
 
     // stage [wbeg, wend + n - 1) symbols with 16-byte loads
@@ -221,25 +228,34 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
           else cnt_add<CT>(p.cnt, cid, (CT)1);
         } else if (ins < 0) {
-          s_over = 1;
-          if (pset_insert(p, c.file, cid)) cnt_add<CT>(p.cnt, cid, (CT)1);
+          emit(wbeg, cid);
         }
       }
     }
     __syncthreads();
-    const bool direct = !c.multi && !s_over;
     for (uint32_t i = tid; i < p.set_cap; i += bs) {
       const uint32_t cid = s_set[i];
       if (cid == LDS_EMPTY) continue;
       if (OCC) {
         cnt_add<CT>(p.cnt, cid, (CT)s_cnt[i]);
         s_cnt[i] = 0;
-      } else if (direct || pset_insert(p, c.file, cid)) {
-        cnt_add<CT>(p.cnt, cid, (CT)1);
+      } else {
+        emit(wbeg, cid);
       }
       s_set[i] = LDS_EMPTY;
     }
     __syncthreads();
+    if (!OCC) {
+      if (tid == 0) {
+        p.nrec[c.fci] = s_nrec;
+        s_nrec = 0;
+      }
+      for (uint32_t b = tid; b < p.nb1; b += bs) {
+        p.hist1[(uint64_t)b * p.nct + c.fci] = s_h1[b];
+        s_h1[b] = 0;
+      }
+      __syncthreads();
+    }
   }
 }
 
