@@ -205,11 +205,11 @@ void ig_destroy(ig_ctx *c) {
       if (x) (void)hipGraphExecDestroy(x);
   c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
-                    &c->status, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
+                    &c->status, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
-    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map_lo, &t.map_hi, &t.map_val, &t.filt};
+    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map, &t.filt};
     for (DevBuf *b : tb) dev_release(c, *b);
   }
   for (auto &e : c->ev)
@@ -354,13 +354,16 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     p.filt = reinterpret_cast<const uint32_t *>(t.filt.p);
     p.filt_words = t.filt_words;
     p.filt_kind = t.filt_kind;
-    p.mkey_lo = reinterpret_cast<const uint64_t *>(t.map_lo.p);
-    p.mkey_hi = reinterpret_cast<const uint64_t *>(t.map_hi.p);
-    p.mval = reinterpret_cast<const uint32_t *>(t.map_val.p);
+    p.map = reinterpret_cast<const uint32_t *>(t.map.p);
     p.mmask = t.map_mask;
+    p.rank_bits = t.rank_bits;
+    p.tkeys_lo = reinterpret_cast<const uint64_t *>(t.lo.p);
+    p.tkeys_hi = reinterpret_cast<const uint64_t *>(t.hi.p);
   }
   p.set_cap = c->lc.set_cap;
   p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
+  // the LDS check assumes the largest level-1 histogram (256 buckets per wavefront)
+  p.hist_words = occ ? 0u : (c->lc.block / 64) * 256u;
   if (scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
                      (unsigned long long)scan_lds_bytes(p, mode, occ));
@@ -398,15 +401,19 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
         c->rec_cap = (guess + floor_cap + T - 1) / T * T;
       }
       const uint64_t cap = c->rec_cap, ntmax = cap / T;
+      const uint32_t ncol = dedup_ncol(nct);
       const uint64_t n1 = (uint64_t)sh.nb1 * nct, n2 = ntmax * sh.nb2;
-      const uint64_t tmp = std::max(dedup_scan_tmp_entries(n1), dedup_scan_tmp_entries(n2));
+      const uint64_t tmp = std::max<uint64_t>(std::max<uint64_t>((uint64_t)sh.nb1 * ncol + 1, dedup_scan_tmp_entries(n2)),
+                                              dedup_scan_tmp_entries((uint64_t)sh.nb1 * sh.nb2));
       if (dev_reserve(c, c->rec0, (c->total_syms + 16) * 4) || dev_reserve(c, c->nrec, std::max<uint64_t>(nct, 1) * 4) ||
-          dev_reserve(c, c->hist1, std::max<uint64_t>(n1, 1) * 4) || dev_reserve(c, c->g1, (n1 + 1) * 8) ||
+          dev_reserve(c, c->hist1, std::max<uint64_t>(n1, 1) * 4) || dev_reserve(c, c->g1, std::max<uint64_t>(n1, 1) * 8) ||
           dev_reserve(c, c->scan_tmp, tmp * 8) || dev_reserve(c, c->base1, ((uint64_t)sh.nb1 + 1) * 8) ||
-          dev_reserve(c, c->bend, (uint64_t)sh.nb1 * 8) || dev_reserve(c, c->dscal, 64) ||
+          dev_reserve(c, c->bend, (uint64_t)sh.nb1 * 8) || dev_reserve(c, c->bshift, (uint64_t)sh.nb1 * 8) ||
+          dev_reserve(c, c->dscal, 64) ||
           dev_reserve(c, c->l1, cap * sh.w1) || dev_reserve(c, c->l2, cap * sh.w2) ||
           dev_reserve(c, c->hist2, n2 * 4) || dev_reserve(c, c->g2, (n2 + 1) * 8) ||
-          dev_reserve(c, c->fin, ((uint64_t)sh.nb1 * sh.nb2 + 1) * 8))
+          dev_reserve(c, c->fin, ((uint64_t)sh.nb1 * sh.nb2 + 1) * 8) ||
+          dev_reserve(c, c->nsegs, (uint64_t)sh.nb1 * sh.nb2 * 4) || dev_reserve(c, c->seg0, ((uint64_t)sh.nb1 * sh.nb2 + 1) * 8))
         return IG_ENOMEM;
       dp.chunks = reinterpret_cast<const Chunk *>(c->chunks_file.p);
       dp.nct = nct;
@@ -421,8 +428,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       dp.hist1 = reinterpret_cast<const uint32_t *>(c->hist1.p);
       dp.g1 = reinterpret_cast<uint64_t *>(c->g1.p);
       dp.scan_tmp = reinterpret_cast<uint64_t *>(c->scan_tmp.p);
+      dp.ncol = ncol;
       dp.base1 = reinterpret_cast<uint64_t *>(c->base1.p);
       dp.bend = reinterpret_cast<uint64_t *>(c->bend.p);
+      dp.bshift = reinterpret_cast<uint64_t *>(c->bshift.p);
       dp.dscal = reinterpret_cast<uint64_t *>(c->dscal.p);
       dp.l1 = c->l1.p;
       dp.l2 = c->l2.p;
@@ -431,6 +440,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       dp.hist2 = reinterpret_cast<uint32_t *>(c->hist2.p);
       dp.g2 = reinterpret_cast<uint64_t *>(c->g2.p);
       dp.fin = reinterpret_cast<uint64_t *>(c->fin.p);
+      dp.nseg = reinterpret_cast<uint32_t *>(c->nsegs.p);
+      dp.seg0 = reinterpret_cast<uint64_t *>(c->seg0.p);
       dp.cnt = c->cnt.p;
       dp.nc = nc;
       dp.status = reinterpret_cast<uint32_t *>(c->status.p);
@@ -440,6 +451,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       p.nct = nct;
       p.low1 = sh.low1;
       p.nb1 = sh.nb1;
+      p.hist_words = (c->lc.block / 64) * sh.nb1;
+      p.b1bits = (uint32_t)__builtin_ctz(sh.nb1);
+      dp.b1bits = p.b1bits;
+      dp.b2bits = (uint32_t)__builtin_ctz(sh.nb2);
       if (check_hip(c, prepare_dedup(sh.low2), "counting attributes")) return IG_EDEVICE;
     }
     const uint64_t kmax = std::min<uint64_t>(kmax0, nc);
@@ -475,10 +490,9 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     auto stage = [&](int k) -> hipError_t {
       hipError_t e = hipSuccess;
       if (k == 0) {
-        // Eq. 2 counts are written whole by the counting stage; Eq. 1 adds into zeroed counters
-        if (occ)
-          e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
-                      : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
+        // counters start at zero (Eq. 2 buckets counted in segments add into them)
+        e = count64 ? launch_fill_u64(reinterpret_cast<uint64_t *>(p.cnt), nc, 0, s)
+                    : launch_fill_u32(reinterpret_cast<uint32_t *>(p.cnt), nc, 0, s);
         if (e == hipSuccess && mode == MODE_SPARSE) e = launch_fill_u32(p.tstate, c->tkey_slots, 0, s);
         if (e == hipSuccess) e = launch_fill_u32(p.status, 16, 0, s);
         if (e == hipSuccess) e = launch_fill_u32(p.qctr, 16, 0, s);
@@ -523,7 +537,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       const uint64_t extra[] = {n, k_keep, kmax, nc, (uint64_t)mode, (uint64_t)kw, (uint64_t)occ, (uint64_t)count64,
                                 sel_count_bits, grid, block, c->rec_cap, c->tkey_slots, c->alloc_gen,
                                 nt.map_mask, nt.filt_words, nt.filt_kind,
-                                (uint64_t)(uintptr_t)nt.lo.p, (uint64_t)(uintptr_t)nt.map_val.p, (uint64_t)(uintptr_t)nt.filt.p};
+                                (uint64_t)(uintptr_t)nt.lo.p, (uint64_t)(uintptr_t)nt.map.p, (uint64_t)(uintptr_t)nt.filt.p};
       std::string key(reinterpret_cast<const char *>(&p), sizeof p);
       key.append(reinterpret_cast<const char *>(&sp), sizeof sp);
       key.append(reinterpret_cast<const char *>(&dp), sizeof dp);

@@ -7,20 +7,22 @@
 // removed.  Records are laid out in file order of the chunks, so that every
 // candidate range below keeps the records of one sequence together:
 //
-//   1. exclusive scan of the level-1 histograms ([bucket][chunk], chunk in file
-//      order) and per-bucket bases, each bucket padded to a whole number of
-//      tiles;
+//   1. a column scan of the level-1 histograms (rows = chunks in file order) in
+//      bucket-major order, and per-bucket bases, each bucket padded to a whole
+//      number of tiles;
 //   2. gather: each chunk's records go to its run in its level-1 bucket, tagged
 //      with the sequence id (runs of one bucket follow the file order);
 //   3. a stable split of every level-1 bucket on the next b2 bits (per-tile
 //      histograms, a scan, and a scatter ranked with wavefront ballots, so the
 //      order inside each final bucket is still the file order);
-//   4. one workgroup per final bucket of at most 2^low2 candidates counts, in
-//      LDS, the distinct sequences of each candidate: a record is new unless
-//      the previous record of its candidate came from the same sequence (the
-//      sequence ids along a bucket never decrease), with a small per-round hash
-//      resolving duplicates that arrive in the same round.  The counts are then
-//      written with plain stores: every candidate belongs to exactly one bucket.
+//   4. one wavefront per final bucket (or per segment of a large bucket, cut at
+//      sequence boundaries) counts, in LDS, the distinct sequences of each of
+//      its at most 2^low2 candidates: a record is new unless the previous record
+//      of its candidate came from the same sequence (sequence ids never decrease
+//      along a bucket).  Within a round of 64 records the previous record of
+//      the same candidate is found with ballots over the candidate bits.  A
+//      bucket counted whole is written with plain stores (every candidate
+//      belongs to exactly one bucket); segments add their counts atomically.
 //
 // Every kernel takes its sizes from device memory (record totals are only known
 // after the scan) and loops over fixed grids, so the sequence of launches can
@@ -34,8 +36,9 @@ namespace ig {
 static constexpr uint32_t TILE = 4096;          // records per level-2 tile
 static constexpr uint32_t SCAN_SEG = 4096;      // elements per block of the generic scan
 static constexpr uint32_t P2_BLOCK = 512;       // threads of the level-2 kernels
-static constexpr uint32_t CNT_BLOCK = 512;      // threads of the count kernel
-static constexpr uint32_t CNT_HASH = 1024;      // per-round pair hash slots (>= 2 x CNT_BLOCK)
+static constexpr uint32_t NCOL_MAX = 1024;      // chunk groups of the column scan
+static constexpr uint32_t SEG = 32768;          // records per counting segment (buckets are cut into segments)
+static constexpr uint32_t CNT_LDS = 64 * 1024;  // LDS of one count workgroup
 
 template <typename R> struct Rec;
 template <> struct Rec<uint32_t> {
@@ -58,9 +61,19 @@ __device__ __forceinline__ bool rec_overflow(const DedupParams &d) {
 }
 
 // ------------------------------------------------------------------ generic exclusive scan u32 -> u64
-__global__ void __launch_bounds__(256) k_xscan_reduce(const uint32_t *in, uint64_t n, uint64_t *part) {
+// The element count is n, or min(n, ndev[0] * mult) when ndev is given (a count only the device knows).
+__device__ __forceinline__ uint64_t scan_len(uint64_t n, const uint64_t *ndev, uint32_t mult) {
+  if (!ndev) return n;
+  const uint64_t m = ndev[0] * mult;
+  return m < n ? m : n;
+}
+
+__global__ void __launch_bounds__(256) k_xscan_reduce(const uint32_t *in, uint64_t n0, const uint64_t *ndev, uint32_t mult,
+                                                      uint64_t *part) {
   __shared__ uint64_t s[256];
+  const uint64_t n = scan_len(n0, ndev, mult);
   const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_SEG;
+  if (b0 >= n) return;
   uint64_t acc = 0;
   for (uint32_t i = threadIdx.x; i < SCAN_SEG; i += 256)
     if (b0 + i < n) acc += in[b0 + i];
@@ -73,7 +86,8 @@ __global__ void __launch_bounds__(256) k_xscan_reduce(const uint32_t *in, uint64
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// exclusive scan of np partials in place (one workgroup), total to *total
+// exclusive scan of np partials in place (one workgroup), total to *total; with ndev, np and
+// the total's position follow the device count (out + n)
 __global__ void __launch_bounds__(1024) k_xscan_top(uint64_t *part, uint64_t np, uint64_t *total) {
   __shared__ uint64_t s[1024];
   const uint32_t t = threadIdx.x;
@@ -97,9 +111,38 @@ __global__ void __launch_bounds__(1024) k_xscan_top(uint64_t *part, uint64_t np,
   if (t == 1023) *total = s[1023];
 }
 
-__global__ void __launch_bounds__(256) k_xscan_apply(const uint32_t *in, uint64_t n, const uint64_t *part, uint64_t *out) {
+__global__ void __launch_bounds__(1024) k_xscan_top_d(uint64_t *part, uint64_t n0, const uint64_t *ndev, uint32_t mult,
+                                                      uint64_t *out) {
+  __shared__ uint64_t s[1024];
+  const uint64_t n = scan_len(n0, ndev, mult);
+  const uint64_t np = (n + SCAN_SEG - 1) / SCAN_SEG;
+  const uint32_t t = threadIdx.x;
+  const uint64_t per = (np + 1023) / 1024, lo = t * per, hi = lo + per < np ? lo + per : np;
+  uint64_t acc = 0;
+  for (uint64_t i = lo; i < hi; i++) acc += part[i];
+  s[t] = acc;
+  __syncthreads();
+  for (uint32_t o = 1; o < 1024; o <<= 1) {
+    const uint64_t x = t >= o ? s[t - o] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  uint64_t run = s[t] - acc;
+  for (uint64_t i = lo; i < hi; i++) {
+    const uint64_t v = part[i];
+    part[i] = run;
+    run += v;
+  }
+  if (t == 1023) out[n] = s[1023];
+}
+
+__global__ void __launch_bounds__(256) k_xscan_apply(const uint32_t *in, uint64_t n0, const uint64_t *ndev, uint32_t mult,
+                                                     const uint64_t *part, uint64_t *out) {
   __shared__ uint64_t s[256];
   constexpr uint32_t PER = SCAN_SEG / 256;
+  const uint64_t n = scan_len(n0, ndev, mult);
+  if ((uint64_t)blockIdx.x * SCAN_SEG >= n) return;
   const uint64_t b0 = (uint64_t)blockIdx.x * SCAN_SEG + (uint64_t)threadIdx.x * PER;
   uint32_t v[PER];
   uint64_t acc = 0;
@@ -122,30 +165,58 @@ __global__ void __launch_bounds__(256) k_xscan_apply(const uint32_t *in, uint64_
   }
 }
 
-// out[0..n) = exclusive prefix sums of in, out[n] = total
-static hipError_t xscan(const uint32_t *in, uint64_t n, uint64_t *part, uint64_t *out, hipStream_t s) {
-  const uint64_t nb = (n + SCAN_SEG - 1) / SCAN_SEG;
+// out[0..n) = exclusive prefix sums of in, out[n] = total; n = min(n_max, ndev[0] * mult) when
+// ndev is given (the grid covers n_max, blocks past n return at once)
+static hipError_t xscan(const uint32_t *in, uint64_t n_max, uint64_t *part, uint64_t *out, hipStream_t s,
+                        const uint64_t *ndev = nullptr, uint32_t mult = 1) {
+  const uint64_t nb = (n_max + SCAN_SEG - 1) / SCAN_SEG;
   if (nb) {
-    hipLaunchKernelGGL(k_xscan_reduce, dim3((uint32_t)nb), dim3(256), 0, s, in, n, part);
+    hipLaunchKernelGGL(k_xscan_reduce, dim3((uint32_t)nb), dim3(256), 0, s, in, n_max, ndev, mult, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_xscan_top, dim3(1), dim3(1024), 0, s, part, nb, out + n);
+  hipLaunchKernelGGL(k_xscan_top_d, dim3(1), dim3(1024), 0, s, part, n_max, ndev, mult, out);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !nb) return e;
-  hipLaunchKernelGGL(k_xscan_apply, dim3((uint32_t)nb), dim3(256), 0, s, in, n, part, out);
+  hipLaunchKernelGGL(k_xscan_apply, dim3((uint32_t)nb), dim3(256), 0, s, in, n_max, ndev, mult, part, out);
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ level-1 column scan
+// Column c of hist1 ([chunk][bucket]) summed over chunk group w -> part[b * ncol + w].
+__global__ void __launch_bounds__(256) k_col_reduce(DedupParams d) {
+  const uint32_t w = blockIdx.x, per = (d.nct + d.ncol - 1) / d.ncol;
+  const uint32_t c0 = w * per, c1 = c0 + per < d.nct ? c0 + per : d.nct;
+  for (uint32_t b = threadIdx.x; b < d.nb1; b += 256) {
+    uint64_t acc = 0;
+    for (uint32_t ci = c0; ci < c1; ci++) acc += d.hist1[(uint64_t)ci * d.nb1 + b];
+    d.scan_tmp[(uint64_t)b * d.ncol + w] = acc;
+  }
+}
+// after the partials are scanned: g1[ci][b] = records before (b, ci) in bucket-major order
+__global__ void __launch_bounds__(256) k_col_apply(DedupParams d) {
+  const uint32_t w = blockIdx.x, per = (d.nct + d.ncol - 1) / d.ncol;
+  const uint32_t c0 = w * per, c1 = c0 + per < d.nct ? c0 + per : d.nct;
+  for (uint32_t b = threadIdx.x; b < d.nb1; b += 256) {
+    uint64_t run = d.scan_tmp[(uint64_t)b * d.ncol + w];
+    for (uint32_t ci = c0; ci < c1; ci++) {
+      d.g1[(uint64_t)ci * d.nb1 + b] = run;
+      run += d.hist1[(uint64_t)ci * d.nb1 + b];
+    }
+  }
+}
+
 // ------------------------------------------------------------------ level-1 bases
-// g1 = scan of hist1 laid out [bucket][chunk]; bucket b's records start at
-// base1[b] (a multiple of TILE) and end at bend[b].
+// Bucket b's records start at base1[b] (a multiple of TILE) and end at bend[b].
 __global__ void __launch_bounds__(256) k_bases(DedupParams d) {
   __shared__ uint64_t s[256];
   const uint32_t t = threadIdx.x;
-  uint64_t tot = 0, pad = 0;
+  const uint64_t total = d.scan_tmp[(uint64_t)d.nb1 * d.ncol];
+  uint64_t start = 0, tot = 0, pad = 0;
   if (t < d.nb1) {
-    tot = d.g1[(uint64_t)(t + 1) * d.nct] - d.g1[(uint64_t)t * d.nct];
+    start = d.scan_tmp[(uint64_t)t * d.ncol];
+    const uint64_t next = t + 1 < d.nb1 ? d.scan_tmp[(uint64_t)(t + 1) * d.ncol] : total;
+    tot = next - start;
     pad = (tot + TILE - 1) / TILE * TILE;
   }
   s[t] = pad;
@@ -159,20 +230,19 @@ __global__ void __launch_bounds__(256) k_bases(DedupParams d) {
   if (t < d.nb1) {
     d.base1[t] = s[t] - pad;
     d.bend[t] = s[t] - pad + tot;
+    d.bshift[t] = (s[t] - pad) - start;   // modulo 2^64
   }
   if (t == 255) {
     const uint64_t padded = s[255];
     d.base1[d.nb1] = padded;
-    d.dscal[0] = d.g1[(uint64_t)d.nb1 * d.nct];   // records
-    d.dscal[1] = padded / TILE;                     // tiles
+    d.dscal[0] = total;
+    d.dscal[1] = padded / TILE;
     d.dscal[2] = padded;
     if (padded > d.cap) atomicOr(d.status, ST_REC_OVF);
   }
 }
 
 // ------------------------------------------------------------------ level-1 gather
-// Each workgroup takes a contiguous range of chunks (file order), so the strided
-// reads of g1 for neighbouring chunks share cache lines.
 template <typename R1>
 __global__ void __launch_bounds__(256) k_gather(DedupParams d) {
   __shared__ uint64_t s_base[256];
@@ -187,15 +257,16 @@ __global__ void __launch_bounds__(256) k_gather(DedupParams d) {
     const Chunk c = d.chunks[ci];
     const uint32_t n = d.nrec[ci] < c.nsym ? d.nrec[ci] : c.nsym;   // a chunk records at most one per window
     if (n == 0) continue;   // uniform across the workgroup
-    if (tid < d.nb1) {
-      s_base[tid] = d.base1[tid] + (d.g1[(uint64_t)tid * d.nct + ci] - d.g1[(uint64_t)tid * d.nct]);
-      s_cur[tid] = 0;
+    for (uint32_t b = tid; b < d.nb1; b += 256) {
+      s_base[b] = d.g1[(uint64_t)ci * d.nb1 + b] + d.bshift[b];
+      s_cur[b] = 0;
     }
     __syncthreads();
     const uint32_t *src = d.rec0 + c.s0;
     for (uint32_t i = tid; i < n; i += 256) {
       const uint32_t cid = src[i];
-      const uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
+      uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
+      if (b >= d.nb1) b = d.nb1 - 1;   // (only a corrupt record could exceed the candidate space)
       const uint32_t k = atomicAdd(s_cur + b, 1u);
       const uint64_t at = s_base[b] + k;
       if (at < d.cap) out[at] = Rec<R1>::pack(c.file, cid & m1, d.low1);
@@ -232,11 +303,7 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_hist(DedupParams d) {
   const uint64_t ntiles = d.dscal[1];
   const R1 *in = reinterpret_cast<const R1 *>(d.l1);
   const uint32_t dm = d.nb2 - 1;
-  for (uint64_t t = blockIdx.x; t < d.ntmax; t += gridDim.x) {
-    if (t >= ntiles) {
-      for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) d.hist2[t * d.nb2 + k] = 0;
-      continue;
-    }
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t pos = t * TILE;
     const uint32_t b = tile_bucket(s_base1, d.nb1, pos);
     const uint64_t tb = s_base1[b] / TILE, ntb = (s_base1[b + 1] - s_base1[b]) / TILE, tl = t - tb;
@@ -259,7 +326,7 @@ __global__ void k_fin(DedupParams d) {
   const uint32_t nf = d.nb1 * d.nb2;
   for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f <= nf; f += gridDim.x * blockDim.x) {
     if (f == nf) {
-      d.fin[nf] = d.g2[d.ntmax * d.nb2];
+      d.fin[nf] = d.g2[d.dscal[1] * d.nb2];
       continue;
     }
     const uint32_t b = f / d.nb2, d2 = f - b * d.nb2;
@@ -269,19 +336,22 @@ __global__ void k_fin(DedupParams d) {
 }
 
 // ------------------------------------------------------------------ level-2 stable scatter
+// A tile is cut into one contiguous slice per wavefront (SLICE_ROUNDS rounds of 64 records,
+// kept in registers).  Each wavefront counts its slice's digits, one prefix over the
+// wavefronts (per digit) gives every wavefront its first position, and each wavefront then
+// replays its rounds in order, advancing its own cursors: positions follow the tile order.
+static constexpr uint32_t SLICE_ROUNDS = TILE / P2_BLOCK;   // rounds of 64 per wavefront and tile
 template <typename R1, typename R2>
 __global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
   constexpr uint32_t NW = P2_BLOCK / 64;
   __shared__ uint64_t s_base1[257];
   __shared__ uint64_t s_bend[256];
-  __shared__ uint64_t run[1024];
-  __shared__ uint32_t tot[1024];
-  __shared__ uint32_t wcnt[NW][1024];
+  __shared__ uint64_t dbase[1024];      // the tile's first position of each digit
+  __shared__ uint32_t wcur[NW][1024];   // per-wavefront cursor of each digit, relative to dbase
   if (rec_overflow(d)) return;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (uint32_t i = tid; i <= d.nb1; i += P2_BLOCK) s_base1[i] = d.base1[i];
   for (uint32_t i = tid; i < d.nb1; i += P2_BLOCK) s_bend[i] = d.bend[i];
-  __syncthreads();
   const uint64_t ntiles = d.dscal[1];
   const R1 *in = reinterpret_cast<const R1 *>(d.l1);
   R2 *out = reinterpret_cast<R2 *>(d.l2);
@@ -289,116 +359,165 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
   const uint32_t m2 = d.low2 >= 32 ? 0xFFFFFFFFu : ((1u << d.low2) - 1);
   const uint64_t lt = (1ull << lane) - 1;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcur[k / d.nb2][k % d.nb2] = 0;
+    __syncthreads();
     const uint64_t pos = t * TILE;
     const uint32_t b = tile_bucket(s_base1, d.nb1, pos);
     const uint64_t tb = s_base1[b] / TILE, ntb = (s_base1[b + 1] - s_base1[b]) / TILE, tl = t - tb;
     const uint64_t hi = pos + TILE < s_bend[b] ? pos + TILE : s_bend[b];
-    for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) run[k] = d.g2[tb * d.nb2 + k * ntb + tl];
-    for (uint64_t s0 = pos; s0 < hi; s0 += P2_BLOCK) {
-      const uint64_t i = s0 + tid;
+    const uint64_t s0 = pos + (uint64_t)w * SLICE_ROUNDS * 64;
+    uint32_t rf[SLICE_ROUNDS], rc[SLICE_ROUNDS], rd[SLICE_ROUNDS];
+    uint64_t rs[SLICE_ROUNDS];
+    // pass 1: this wavefront's digit counts
+#pragma unroll
+    for (uint32_t q = 0; q < SLICE_ROUNDS; q++) {
+      const uint64_t i = s0 + q * 64 + lane;
       const bool valid = i < hi;
-      uint32_t file = 0, cl = 0, dg = 0;
+      rf[q] = 0;
+      rc[q] = 0;
+      rd[q] = 0;
       if (valid) {
         const R1 r = in[i];
-        file = Rec<R1>::file(r, d.low1);
-        cl = Rec<R1>::cl(r, d.low1);
-        dg = (cl >> d.low2) & dm;
+        rf[q] = Rec<R1>::file(r, d.low1);
+        rc[q] = Rec<R1>::cl(r, d.low1);
+        rd[q] = (rc[q] >> d.low2) & dm;
       }
-      for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcnt[k / d.nb2][k % d.nb2] = 0;
-      __syncthreads();
-      // lanes of this wavefront with the same digit, by ballots over the digit bits
-      const uint64_t vm = __ballot(valid);
-      uint64_t same = vm;
-      for (uint32_t j = 0; (1u << j) < d.nb2; j++) {
-        const bool bit = (dg >> j) & 1u;
-        const uint64_t bj = __ballot(valid && bit);
-        same &= bit ? bj : (vm & ~bj);
-      }
-      const uint32_t rank = valid ? (uint32_t)__popcll(same & lt) : 0u;
-      if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(same);
-      __syncthreads();
-      for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) {
-        uint32_t off = 0;
-        for (uint32_t ww = 0; ww < NW; ww++) {
-          const uint32_t x = wcnt[ww][k];
-          wcnt[ww][k] = off;
-          off += x;
-        }
-        tot[k] = off;
-      }
-      __syncthreads();
-      if (valid) {
-        const uint64_t at = run[dg] + wcnt[w][dg] + rank;
-        if (at < d.cap) out[at] = Rec<R2>::pack(file, cl & m2, d.low2);
-      }
-      __syncthreads();
-      for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) run[k] += tot[k];
-      __syncthreads();
+      rs[q] = wave_match(rd[q], d.b2bits, valid);
+      if (valid && (rs[q] & lt) == 0) wcur[w][rd[q]] += (uint32_t)__popcll(rs[q]);
     }
-  }
-}
-
-// ------------------------------------------------------------------ distinct sequences per candidate
-template <typename R2>
-__global__ void __launch_bounds__(CNT_BLOCK) k_count(DedupParams d) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  uint64_t *hk = reinterpret_cast<uint64_t *>(lds);                // CNT_HASH pair keys
-  uint32_t *last = reinterpret_cast<uint32_t *>(hk + CNT_HASH);    // 1 + sequence of the latest record
-  uint32_t *cnt = last + (1u << d.low2);
-  if (rec_overflow(d)) return;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t cb = 1u << d.low2;
-  const R2 *in = reinterpret_cast<const R2 *>(d.l2);
-  uint32_t *gcnt = reinterpret_cast<uint32_t *>(d.cnt);
-  for (uint32_t k = tid; k < CNT_HASH; k += CNT_BLOCK) hk[k] = 0;
-  for (uint32_t k = tid; k < cb; k += CNT_BLOCK) { last[k] = 0; cnt[k] = 0; }
-  __syncthreads();
-  const uint32_t nf = d.nb1 * d.nb2;
-  for (uint32_t f = blockIdx.x; f < nf; f += gridDim.x) {
-    const uint64_t cid0 = (uint64_t)f << d.low2;
-    if (cid0 >= d.nc) break;   // later buckets are beyond the candidate space (and empty)
-    const uint64_t lo = d.fin[f], hi = d.fin[f + 1] < d.cap ? d.fin[f + 1] : d.cap;
-    for (uint64_t s0 = lo; s0 < hi; s0 += CNT_BLOCK) {
-      const uint64_t i = s0 + tid;
+    __syncthreads();
+    // per digit: the tile's first position, then each wavefront's offset from it
+    for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) {
+      dbase[k] = d.g2[tb * d.nb2 + (uint64_t)k * ntb + tl];
+      uint32_t off = 0;
+      for (uint32_t ww = 0; ww < NW; ww++) {
+        const uint32_t x = wcur[ww][k];
+        wcur[ww][k] = off;
+        off += x;
+      }
+    }
+    __syncthreads();
+    // pass 2: replay in order
+#pragma unroll
+    for (uint32_t q = 0; q < SLICE_ROUNDS; q++) {
+      const uint64_t i = s0 + q * 64 + lane;
       const bool valid = i < hi;
-      uint32_t f1 = 0, cl = 0, lp = 0;
       if (valid) {
-        const R2 r = in[i];
-        f1 = Rec<R2>::file(r, d.low2) + 1;
-        cl = Rec<R2>::cl(r, d.low2);
-        lp = last[cl];
+        const uint64_t at = dbase[rd[q]] + wcur[w][rd[q]] + (uint32_t)__popcll(rs[q] & lt);
+        if (at < d.cap) out[at] = Rec<R2>::pack(rf[q], rc[q] & m2, d.low2);
       }
-      __syncthreads();
-      bool won = false;
-      uint32_t slot = 0;
-      if (valid) {
-        const uint64_t key = ((uint64_t)f1 << 32) | cl;
-        slot = (uint32_t)(mix64(key) & (CNT_HASH - 1));
-        for (;;) {
-          const unsigned long long old = atomicCAS(reinterpret_cast<unsigned long long *>(hk + slot), 0ull,
-                                                   (unsigned long long)key);
-          if (old == 0ull) { won = true; break; }
-          if (old == key) break;
-          slot = (slot + 1) & (CNT_HASH - 1);
-        }
-        if (won && lp != f1) atomicAdd(cnt + cl, 1u);
-        atomicMax(last + cl, f1);
-      }
-      __syncthreads();
-      if (won) hk[slot] = 0;
-      __syncthreads();
-    }
-    const uint64_t cend = cid0 + cb < d.nc ? cid0 + cb : d.nc;
-    for (uint32_t k = tid; k < cb; k += CNT_BLOCK) {
-      if (cid0 + k < cend) gcnt[cid0 + k] = cnt[k];
-      cnt[k] = 0;
-      last[k] = 0;
+      // every lane has read its cursor before the group's first lane advances it
+      __builtin_amdgcn_wave_barrier();
+      if (valid && (rs[q] & lt) == 0) wcur[w][rd[q]] += (uint32_t)__popcll(rs[q]);
+      __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
   }
 }
 
-size_t count_lds_bytes(uint32_t low2) { return (size_t)CNT_HASH * 8 + ((size_t)2 << low2) * 4; }
+// ------------------------------------------------------------------ distinct sequences per candidate
+template <typename R2>
+__device__ __forceinline__ uint32_t rec_file(const R2 *in, uint64_t i, uint32_t low2) {
+  return Rec<R2>::file(in[i], low2);
+}
+
+// first index in [x, hi) whose sequence differs from the record at x - 1 (lo and hi map to themselves)
+template <typename R2>
+__device__ uint64_t snap_to_sequence(const R2 *in, uint64_t lo, uint64_t hi, uint64_t x, uint32_t low2) {
+  if (x <= lo || x >= hi) return x <= lo ? lo : hi;
+  const uint32_t fprev = rec_file(in, x - 1, low2);
+  uint64_t a = x, b = hi;   // first index with sequence > fprev lies in [a, b]
+  while (a < b) {
+    const uint64_t mid = a + ((b - a) >> 1);
+    if (rec_file(in, mid, low2) > fprev) b = mid;
+    else a = mid + 1;
+  }
+  return a;
+}
+
+// segments per final bucket (0 beyond the candidate space)
+__global__ void k_nseg(DedupParams d) {
+  if (rec_overflow(d)) return;
+  const uint32_t nf = d.nb1 * d.nb2;
+  for (uint32_t f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x) {
+    const uint64_t cid0 = (uint64_t)f << d.low2;
+    const uint64_t lo = d.fin[f], hi = d.fin[f + 1];
+    const uint64_t size = hi > lo ? hi - lo : 0;
+    d.nseg[f] = cid0 >= d.nc ? 0u : (uint32_t)(size > SEG ? (size + SEG - 1) / SEG : 1);
+  }
+}
+
+// One wavefront per segment (segments of one bucket are cut at sequence
+// boundaries); the waves of a workgroup work independently.
+template <typename R2>
+__global__ void __launch_bounds__(256) k_count(DedupParams d) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const uint32_t cb = 1u << d.low2;
+  uint32_t *last = reinterpret_cast<uint32_t *>(lds) + (size_t)wave * 2 * cb;   // 1 + sequence of the latest record
+  uint32_t *cnt = last + cb;
+  if (rec_overflow(d)) return;
+  const R2 *in = reinterpret_cast<const R2 *>(d.l2);
+  uint32_t *gcnt = reinterpret_cast<uint32_t *>(d.cnt);
+  const uint64_t lt = (1ull << lane) - 1;
+  const uint32_t nf = d.nb1 * d.nb2;
+  const uint64_t nsegs = d.seg0[nf];
+  for (uint64_t g = (uint64_t)blockIdx.x * nw + wave; g < nsegs; g += (uint64_t)gridDim.x * nw) {
+    // bucket of segment g: the last f with seg0[f] <= g
+    uint32_t fl = 0, fh = nf;
+    while (fh - fl > 1) {
+      const uint32_t mid = (fl + fh) >> 1;
+      if (d.seg0[mid] <= g) fl = mid;
+      else fh = mid;
+    }
+    const uint32_t f = fl;
+    const uint64_t j = g - d.seg0[f], nseg = d.seg0[f + 1] - d.seg0[f];
+    const uint64_t cid0 = (uint64_t)f << d.low2;
+    const uint64_t lo = d.fin[f], hi = d.fin[f + 1] < d.cap ? d.fin[f + 1] : d.cap;
+    const uint64_t size = hi > lo ? hi - lo : 0;
+    const uint64_t a = snap_to_sequence(in, lo, hi, lo + size * j / nseg, d.low2);
+    const uint64_t b = snap_to_sequence(in, lo, hi, lo + size * (j + 1) / nseg, d.low2);
+    if (nseg > 1 && a >= b) continue;   // one sequence spans this cut: the neighbouring segment has it
+    for (uint32_t k = lane; k < cb; k += 64) { last[k] = 0; cnt[k] = 0; }
+    // records of the next round are loaded while this round is processed
+    R2 nxt = 0;
+    if (a + lane < b) nxt = in[a + lane];
+    for (uint64_t s0 = a; s0 < b; s0 += 64) {
+      const bool valid = s0 + lane < b;
+      const R2 r = nxt;
+      if (s0 + 64 + lane < b) nxt = in[s0 + 64 + lane];
+      uint32_t f1 = 0, cl = 0;
+      if (valid) {
+        f1 = Rec<R2>::file(r, d.low2) + 1;
+        cl = Rec<R2>::cl(r, d.low2);
+      }
+      // lanes holding the same candidate
+      const uint64_t same = wave_match(cl, d.low2, valid);
+      const uint64_t below = same & lt;
+      const uint32_t pred = below ? 63u - (uint32_t)__clzll((unsigned long long)below) : lane;
+      const uint32_t fpred = (uint32_t)__shfl((int)f1, (int)pred);
+      const uint32_t lp = valid ? last[cl] : 0u;
+      const bool isnew = valid && (below ? fpred != f1 : lp != f1);
+      const bool islast = valid && (same >> lane) == 1ull;   // highest lane of its group
+      if (isnew) atomicAdd(cnt + cl, 1u);
+      if (islast) last[cl] = f1;
+    }
+    const uint64_t cend = cid0 + cb < d.nc ? cid0 + cb : d.nc;
+    for (uint32_t k = lane; k < cb; k += 64) {
+      if (cid0 + k >= cend) break;
+      if (nseg == 1) gcnt[cid0 + k] = cnt[k];
+      else if (cnt[k]) atomicAdd(gcnt + cid0 + k, cnt[k]);
+    }
+  }
+}
+
+static uint32_t count_waves(uint32_t low2) {
+  const size_t per_wave = (size_t)8 << low2;
+  size_t w = CNT_LDS / per_wave;
+  if (w > 4) w = 4;
+  return w ? (uint32_t)w : 1u;
+}
+size_t count_lds_bytes(uint32_t low2) { return (size_t)count_waves(low2) * ((size_t)8 << low2); }
 
 // ------------------------------------------------------------------ host side
 DedupShape dedup_shape(uint64_t nc, uint64_t m) {
@@ -406,7 +525,7 @@ DedupShape dedup_shape(uint64_t nc, uint64_t m) {
   auto bits_of = [](uint64_t x) { uint32_t b = 0; while (b < 64 && (x >> b)) b++; return b; };
   const uint32_t cbits = std::max<uint32_t>(1, bits_of(nc - 1));
   const uint32_t fbits = std::max<uint32_t>(1, bits_of(m ? m - 1 : 0));
-  uint32_t low2 = std::min<uint32_t>(13, cbits);
+  uint32_t low2 = std::min<uint32_t>(11, cbits);   // 2^11 candidates: 16 KB of LDS per wavefront
   uint32_t split = cbits - low2;
   if (split > 18) { low2 = cbits - 18; split = 18; }
   // level 1 as fine as needed to pack its records into 32 bits, at most 8 bits
@@ -425,10 +544,17 @@ DedupShape dedup_shape(uint64_t nc, uint64_t m) {
 }
 
 uint64_t dedup_tile() { return TILE; }
+uint32_t dedup_ncol(uint32_t nct) { return std::max<uint32_t>(1, std::min<uint32_t>(NCOL_MAX, nct)); }
 
 hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
-  hipError_t e = xscan(d.hist1, (uint64_t)d.nb1 * d.nct, d.scan_tmp, d.g1, s);
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  hipLaunchKernelGGL(k_col_reduce, dim3(d.ncol), dim3(256), 0, s, d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const uint64_t np = (uint64_t)d.nb1 * d.ncol;
+  hipLaunchKernelGGL(k_xscan_top, dim3(1), dim3(1024), 0, s, d.scan_tmp, np, d.scan_tmp + np);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_apply, dim3(d.ncol), dim3(256), 0, s, d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bases, dim3(1), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t grid = (uint32_t)n_cu * 4;
@@ -439,7 +565,7 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if (d.w1 == 4) hipLaunchKernelGGL(k_p2_hist<uint32_t>, dim3(g2), dim3(P2_BLOCK), 0, s, d);
   else hipLaunchKernelGGL(k_p2_hist<uint64_t>, dim3(g2), dim3(P2_BLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  e = xscan(d.hist2, d.ntmax * d.nb2, d.scan_tmp, d.g2, s);
+  e = xscan(d.hist2, d.ntmax * d.nb2, d.scan_tmp, d.g2, s, d.dscal + 1, d.nb2);   // live tiles only
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin, dim3((d.nb1 * d.nb2 + 256) / 256), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -448,11 +574,17 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   else if (d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
   else hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds = count_lds_bytes(d.low2);
+  // segments of at most SEG records, cut at sequence boundaries, so that a hot bucket is shared out
   const uint32_t nf = d.nb1 * d.nb2;
-  const uint32_t gc = nf < (uint32_t)n_cu * 2 ? nf : (uint32_t)n_cu * 2;
-  if (d.w2 == 4) hipLaunchKernelGGL(k_count<uint32_t>, dim3(gc), dim3(CNT_BLOCK), lds, s, d);
-  else hipLaunchKernelGGL(k_count<uint64_t>, dim3(gc), dim3(CNT_BLOCK), lds, s, d);
+  hipLaunchKernelGGL(k_nseg, dim3((nf + 255) / 256), dim3(256), 0, s, d);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  e = xscan(d.nseg, nf, d.scan_tmp, d.seg0, s);
+  if (e != hipSuccess) return e;
+  const uint32_t wv = count_waves(d.low2);
+  const uint32_t gc = (uint32_t)n_cu * 2;
+  const size_t lds = count_lds_bytes(d.low2);
+  if (d.w2 == 4) hipLaunchKernelGGL(k_count<uint32_t>, dim3(gc), dim3(64 * wv), lds, s, d);
+  else hipLaunchKernelGGL(k_count<uint64_t>, dim3(gc), dim3(64 * wv), lds, s, d);
   return hipGetLastError();
 }
 

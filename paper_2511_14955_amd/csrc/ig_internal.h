@@ -15,8 +15,9 @@
 //      small unfiltered:   cid = key                       (n*b <= 26)
 //      large unfiltered:   cid = slot of the key in a device hash table
 //  * retained table: keys (lo/hi u64 arrays) and counts (u64), in the order
-//    (count desc, key asc); a hash map key -> rank+1 and a compact filter image
-//    over the same keys serve both the next pass (prefix test) and featurize.
+//    (count desc, key asc); a hash map key -> rank (32-bit slots with a hash
+//    fingerprint, confirmed against the keys) and a compact filter image over
+//    the same keys serve both the next pass (prefix test) and featurize.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -41,6 +42,27 @@ __host__ __device__ __forceinline__ uint64_t hash_key(uint64_t lo, uint64_t hi) 
 __host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
   return x;
+}
+
+// Lanes of this wavefront whose `key` (its low `nbits` bits) equals this lane's, among the
+// valid lanes (the wavefront's analogue of a match instruction: one ballot per key bit).
+// Invalid lanes get the mask of valid lanes sharing their bits, which callers ignore.
+__device__ __forceinline__ uint64_t wave_match(uint32_t key, uint32_t nbits, bool valid) {
+  const uint64_t vm = __ballot(valid);
+  uint64_t same = vm;
+  for (uint32_t q = 0; q < nbits; q++) {
+    const bool bit = (key >> q) & 1u;
+    const uint64_t bq = __ballot(valid && bit);
+    same &= bit ? bq : (vm & ~bq);
+  }
+  return same;
+}
+
+// Key -> rank map: one 32-bit slot per entry, holding rank+1 in its low rank_bits bits and a
+// fingerprint of the key's hash in the rest (empty = 0).  A probe compares fingerprints and
+// only on a match reads the key itself from the table's keys (stored in rank order) to confirm.
+__device__ __forceinline__ uint32_t map_fp(uint64_t h, uint32_t rank_bits) {
+  return rank_bits >= 32 ? 0u : (uint32_t)(h >> (32 + rank_bits));
 }
 
 // ------------------------------------------------------------------ shared structs
@@ -74,10 +96,11 @@ struct ScanParams {
   const uint32_t *filt;
   uint32_t filt_words;           // power of two
   uint32_t filt_kind;
-  // exact map previous key -> rank + 1
-  const uint64_t *mkey_lo, *mkey_hi;
-  const uint32_t *mval;
+  // exact map previous key -> rank (fingerprinted slots; keys confirmed against the table)
+  const uint32_t *map;
   uint64_t mmask;
+  uint32_t rank_bits;            // low bits of a slot holding rank+1
+  const uint64_t *tkeys_lo, *tkeys_hi;   // previous table's keys, in rank order
   // large unfiltered passes: key table
   uint64_t *tkey_lo, *tkey_hi;
   uint32_t *tstate;
@@ -86,10 +109,12 @@ struct ScanParams {
   void *cnt;
   uint32_t *rec;                 // Eq. 2: one u32 slot per symbol; a chunk writes its records at [s0, s0 + nrec)
   uint32_t *nrec;                // Eq. 2: records per chunk (file-order index)
-  uint32_t *hist1;               // Eq. 2: [bucket][chunk] counts of the records' top bits
+  uint32_t *hist1;               // Eq. 2: [chunk][bucket] counts of the records' top bits
   uint32_t nct;                  // chunks in file order (histogram row length)
   uint32_t low1;                 // level-1 bucket = cid >> low1
   uint32_t nb1;                  // level-1 buckets (<= 256)
+  uint32_t b1bits;               // log2(nb1)
+  uint32_t hist_words;           // Eq. 2: LDS words of the per-wavefront level-1 histograms
   uint32_t *status;
   uint32_t set_cap;              // LDS de-duplication set entries (power of two)
   uint32_t stage_bytes;          // LDS staging bytes
@@ -105,13 +130,16 @@ struct DedupParams {
   const Chunk *chunks;           // file order
   uint32_t nct;
   uint32_t nb1, nb2, low1, low2, w1, w2;
+  uint32_t b1bits, b2bits;       // log2(nb1), log2(nb2)
   const uint32_t *rec0;          // the scan's slab
   const uint32_t *nrec;
-  const uint32_t *hist1;         // [nb1][nct]
-  uint64_t *g1;                  // scan of hist1 (nb1*nct + 1)
-  uint64_t *scan_tmp;
+  const uint32_t *hist1;         // [nct][nb1]
+  uint64_t *g1;                  // [nct][nb1]: records before (bucket, chunk) in bucket-major order
+  uint64_t *scan_tmp;            // column partials [nb1][ncol] + total; later the hist2 scan's partials
+  uint32_t ncol;                 // chunk groups of the column scan
   uint64_t *base1;               // nb1 + 1 tile-aligned bucket starts
   uint64_t *bend;                // nb1 bucket ends
+  uint64_t *bshift;              // nb1: base1[b] - (records before bucket b), modulo 2^64
   uint64_t *dscal;               // [0] records, [1] tiles, [2] padded records
   void *l1;
   void *l2;
@@ -120,6 +148,8 @@ struct DedupParams {
   uint32_t *hist2;               // ntmax * nb2
   uint64_t *g2;                  // scan of hist2 (ntmax*nb2 + 1)
   uint64_t *fin;                 // nb1*nb2 + 1 final bucket starts in l2
+  uint32_t *nseg;                // nb1*nb2 counting segments per final bucket
+  uint64_t *seg0;                // nb1*nb2 + 1: scan of nseg
   void *cnt;                     // u32 counts, nc entries
   uint64_t nc;
   uint32_t *status;
@@ -127,6 +157,8 @@ struct DedupParams {
 DedupShape dedup_shape(uint64_t nc, uint64_t m);
 uint64_t dedup_tile();
 uint64_t dedup_scan_tmp_entries(uint64_t n);
+uint32_t dedup_ncol(uint32_t nct);
+size_t count_lds_bytes(uint32_t low2);
 hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s);
 hipError_t prepare_dedup(uint32_t low2);
 
@@ -152,8 +184,9 @@ struct DevBuf {
 // One retained table and its index (exact map key -> rank+1, compact filter image).
 struct TableSet {
   DevBuf lo, hi, cnt;
-  DevBuf map_lo, map_hi, map_val, filt;
+  DevBuf map, filt;               // map: 32-bit fingerprinted slots (rank+1 in the low rank_bits)
   uint64_t kept = 0, map_mask = 0;
+  uint32_t rank_bits = 32;
   uint32_t n = 0, filt_words = 0, filt_kind = 0;
 };
 
@@ -201,7 +234,7 @@ struct ig_ctx {
   ig::DevBuf cnt, tkey_lo, tkey_hi, tstate;
   uint64_t tkey_slots = 0;
   // once-per-sequence counting: slab, per-chunk counts and histograms, bucketed records
-  ig::DevBuf rec0, nrec, hist1, g1, scan_tmp, base1, bend, dscal, l1, l2, hist2, g2, fin;
+  ig::DevBuf rec0, nrec, hist1, g1, scan_tmp, base1, bend, bshift, dscal, l1, l2, hist2, g2, fin, nsegs, seg0;
   uint64_t rec_cap = 0;         // records the bucketed arrays hold (multiple of the tile)
   ig::DevBuf sel_cid, sel_cnt, sel_klo, sel_khi, tie_a, tie_b, sort_tmp, hist, selstate, thist;
 

@@ -46,18 +46,6 @@ template <typename CT> __device__ __forceinline__ void cnt_add(void *cnt, uint32
   __hip_atomic_fetch_add(reinterpret_cast<CT *>(cnt) + cid, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exact lookup in the key -> rank+1 map (capacity >= 2x entries, so a probe run ends).
-template <int KW>
-__device__ __forceinline__ int64_t map_find(const ScanParams &p, uint64_t lo, uint64_t hi, uint64_t h) {
-  uint64_t slot = h & p.mmask;
-  for (;;) {
-    const uint32_t v = p.mval[slot];
-    if (v == 0) return -1;
-    if (p.mkey_lo[slot] == lo && (KW == 1 || p.mkey_hi[slot] == hi)) return (int64_t)v - 1;
-    slot = (slot + 1) & p.mmask;
-  }
-}
-
 // Insert-or-find in the key table of large unfiltered passes; returns the slot,
 // or 0xFFFFFFFF after flagging an overflow.  A slot is claimed (state 0 -> 1),
 // its key words written, then published (state 2); readers wait on state 1.
@@ -92,9 +80,9 @@ __device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t l
 __device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t cid, uint32_t *slot_out) {
   uint32_t h = hash32(cid) & capmask;
   for (int i = 0; i < 64; i++) {
-    const uint32_t old = atomicCAS(s_set + h, LDS_EMPTY, cid);
-    if (old == LDS_EMPTY) { *slot_out = h; return 1; }
-    if (old == cid) { *slot_out = h; return 0; }
+    const uint32_t cur = atomicCAS(s_set + h, LDS_EMPTY, cid);
+    if (cur == LDS_EMPTY) { *slot_out = h; return 1; }
+    if (cur == cid) { *slot_out = h; return 0; }
     h = (h + 1) & capmask;
   }
   return -1;
@@ -110,13 +98,15 @@ __device__ __forceinline__ uint32_t stage_sym(const uint8_t *s_stage, uint64_t g
 template <int B, int KW, int MODE, int OCC, typename CT>
 __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   extern __shared__ __align__(16) uint8_t lds[];
-  __shared__ uint32_t s_h1[256];       // Eq. 2: histogram of this chunk's records (level-1 buckets)
   __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
   uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? p.filt_words : 0);
   uint32_t *s_cnt = s_set + p.set_cap;                 // OCC only
   uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
+  // Eq. 2: histogram of this chunk's records over the level-1 buckets, one copy per
+  // wavefront (a few hot buckets take most records; a shared copy would serialize them)
+  uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256);
   __shared__ uint32_t s_chunk;
 
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
@@ -133,17 +123,19 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     s_set[i] = LDS_EMPTY;
     if (OCC) s_cnt[i] = 0;
   }
-  for (uint32_t i = tid; i < 256; i += bs) {
-    s_code[i] = p.code[i];
-    s_h1[i] = 0;
-  }
+  for (uint32_t i = tid; i < 256; i += bs) s_code[i] = p.code[i];
+  for (uint32_t i = tid; i < p.hist_words; i += bs) s_h1w[i] = 0;
   if (tid == 0) s_nrec = 0;
   __syncthreads();
-  // Eq. 2: append one record of this chunk (slot c.s0 + k, k < windows of the chunk)
+  const uint32_t lane = tid & 63, nwaves = bs >> 6;
+  const uint64_t lanes_below = (1ull << lane) - 1;
+  uint32_t *my_h1 = s_h1w + (tid >> 6) * p.nb1;
+  // Eq. 2: append one record of this chunk (slot c.s0 + k, k < windows of the chunk);
+  // used by threads whose insert found the LDS set full
   auto emit = [&](uint64_t s0, uint32_t cid) {
     const uint32_t k = atomicAdd(&s_nrec, 1u);
     p.rec[s0 + k] = cid;
-    atomicAdd(s_h1 + (p.low1 >= 32 ? 0u : (cid >> p.low1)), 1u);
+    atomicAdd(my_h1 + (p.low1 >= 32 ? 0u : (cid >> p.low1)), 1u);
   };
 
   uint32_t local_iter = 0;
@@ -169,7 +161,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       // no window: an Eq. 2 chunk still reports zero records
       if (!OCC) {
         if (tid == 0) p.nrec[c.fci] = 0;
-        for (uint32_t b = tid; b < p.nb1; b += bs) p.hist1[(uint64_t)b * p.nct + c.fci] = 0;
+        for (uint32_t b = tid; b < p.nb1; b += bs) p.hist1[(uint64_t)c.fci * p.nb1 + b] = 0;
       }
       __syncthreads();
       continue;
@@ -182,7 +174,11 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     const uint64_t a0 = byte_lo & ~15ull;
     const uint64_t a1 = (byte_hi + 15) & ~15ull;
     const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
-    for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs) reinterpret_cast<uint4 *>(s_stage)[i] = src[i];
+    // the corpus streams through once per pass: non-temporal loads keep it from evicting
+    // the key -> rank map from L2
+    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+    for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs)
+      reinterpret_cast<u32x4_t *>(s_stage)[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(src) + i);
     __syncthreads();
 
     const uint32_t per = (uint32_t)((nwin + bs - 1) / bs);
@@ -194,34 +190,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
       const uint64_t sbase = (B == 8) ? a0 : a0;
       for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
-      for (uint64_t t = t_lo; t < t_hi; t++) {
-        const uint64_t g = wbeg + t;
-        k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
-        uint32_t cid;
-        if (MODE == MODE_DENSE) {
-          cid = (uint32_t)k.lo;
-        } else if (MODE == MODE_FILTERED) {
-          const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
-          uint64_t h = 0;
-          if (p.filt_kind == FILT_DIRECT) {
-            if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
-            h = hash_key(plo, phi);
-          } else {
-            h = hash_key(plo, phi);
-            if (p.filt_kind == FILT_BLOOM) {
-              const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
-              const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
-              if ((w & bm) != bm) continue;
-            }
-          }
-          const int64_t r = map_find<KW>(p, plo, phi, h);
-          if (r < 0) continue;
-          const uint32_t last = (uint32_t)(k.lo & ((1u << B) - 1));
-          cid = (uint32_t)r * p.sigma + s_code[last];
-        } else {
-          cid = table_insert(p, k.lo, k.hi);
-          if (cid == 0xFFFFFFFFu) continue;
-        }
+      // one surviving candidate: de-duplicate in the chunk's LDS set
+      auto handle = [&](uint32_t cid) {
         uint32_t slot;
         const int ins = lds_insert(s_set, capmask, cid, &slot);
         if (OCC) {
@@ -230,19 +200,127 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         } else if (ins < 0) {
           emit(wbeg, cid);
         }
+      };
+      if (MODE == MODE_FILTERED) {
+        // Windows are taken RB at a time: every window's key is rolled and filtered and the
+        // first map slot of each survivor is read; then the keys of fingerprint matches are
+        // read from the table; then the probes are resolved.  Up to RB independent reads
+        // per thread are in flight at each step.
+        constexpr int RB = 8;
+        const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
+        for (uint64_t t0 = t_lo; t0 < t_hi; t0 += RB) {
+          uint64_t q_lo[RB], q_hi[RB], q_klo[RB], q_khi[RB], q_slot[RB];
+          uint32_t q_v[RB], q_fp[RB], q_code[RB];
+          uint32_t live = 0, hit = 0;
+#pragma unroll
+          for (int u = 0; u < RB; u++) {
+            q_v[u] = 0;
+            q_fp[u] = 0;
+            q_lo[u] = q_hi[u] = q_klo[u] = q_khi[u] = 0;
+            q_slot[u] = 0;
+            q_code[u] = 0;
+            if (t0 + u >= t_hi) continue;
+            const uint64_t g = wbeg + t0 + u;
+            k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
+            const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
+            uint64_t h = 0;
+            if (p.filt_kind == FILT_DIRECT) {
+              if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
+              h = hash_key(plo, phi);
+            } else {
+              h = hash_key(plo, phi);
+              if (p.filt_kind == FILT_BLOOM) {
+                const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
+                const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+                if ((w & bm) != bm) continue;
+              }
+            }
+            const uint64_t slot = h & p.mmask;
+            q_slot[u] = slot;
+            q_v[u] = p.map[slot];
+            q_fp[u] = map_fp(h, p.rank_bits);
+            q_lo[u] = plo;
+            q_hi[u] = phi;
+            q_code[u] = s_code[(uint32_t)(k.lo & ((1u << B) - 1))];
+            live |= 1u << u;
+          }
+#pragma unroll
+          for (int u = 0; u < RB; u++) {
+            if (!((live >> u) & 1u)) continue;
+            const uint32_t v = q_v[u];
+            if (v != 0 && (p.rank_bits >= 32 || (v >> p.rank_bits) == q_fp[u])) {
+              const uint32_t r = (v & rmask) - 1;
+              q_klo[u] = p.tkeys_lo[r];
+              if (KW == 2) q_khi[u] = p.tkeys_hi[r];
+              hit |= 1u << u;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < RB; u++) {
+            if (!((live >> u) & 1u)) continue;
+            uint64_t slot = q_slot[u];
+            uint32_t v = q_v[u];
+            int64_t r = -1;
+            if (((hit >> u) & 1u) && q_klo[u] == q_lo[u] && (KW == 1 || q_khi[u] == q_hi[u])) {
+              r = (int64_t)(v & rmask) - 1;
+            } else {
+              // rare: the first slot was another key's; continue the linear probe
+              while (v != 0) {
+                slot = (slot + 1) & p.mmask;
+                v = p.map[slot];
+                if (v == 0) break;
+                if (p.rank_bits < 32 && (v >> p.rank_bits) != q_fp[u]) continue;
+                const uint32_t rr = (v & rmask) - 1;
+                if (p.tkeys_lo[rr] == q_lo[u] && (KW == 1 || p.tkeys_hi[rr] == q_hi[u])) {
+                  r = rr;
+                  break;
+                }
+              }
+            }
+            if (r < 0) continue;
+            handle((uint32_t)r * p.sigma + q_code[u]);
+          }
+        }
+      } else {
+        for (uint64_t t = t_lo; t < t_hi; t++) {
+          const uint64_t g = wbeg + t;
+          k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
+          uint32_t cid;
+          if (MODE == MODE_DENSE) {
+            cid = (uint32_t)k.lo;
+          } else {
+            cid = table_insert(p, k.lo, k.hi);
+            if (cid == 0xFFFFFFFFu) continue;
+          }
+          handle(cid);
+        }
       }
     }
     __syncthreads();
+    // set_cap is a multiple of the block, so every lane of a wavefront runs the same iterations
     for (uint32_t i = tid; i < p.set_cap; i += bs) {
       const uint32_t cid = s_set[i];
-      if (cid == LDS_EMPTY) continue;
+      const bool full = cid != LDS_EMPTY;
       if (OCC) {
-        cnt_add<CT>(p.cnt, cid, (CT)s_cnt[i]);
-        s_cnt[i] = 0;
-      } else {
-        emit(wbeg, cid);
+        if (full) {
+          cnt_add<CT>(p.cnt, cid, (CT)s_cnt[i]);
+          s_cnt[i] = 0;
+          s_set[i] = LDS_EMPTY;
+        }
+        continue;
       }
-      s_set[i] = LDS_EMPTY;
+      // one LDS atomic per wavefront reserves the wavefront's consecutive record slots
+      const uint64_t mask = __ballot(full);
+      if (!mask) continue;
+      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&s_nrec, (uint32_t)__popcll(mask));
+      base = __shfl(base, leader);
+      if (full) {
+        __builtin_nontemporal_store(cid, p.rec + wbeg + base + (uint32_t)__popcll(mask & lanes_below));
+        atomicAdd(my_h1 + (p.low1 >= 32 ? 0u : (cid >> p.low1)), 1u);
+        s_set[i] = LDS_EMPTY;
+      }
     }
     __syncthreads();
     if (!OCC) {
@@ -251,8 +329,12 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         s_nrec = 0;
       }
       for (uint32_t b = tid; b < p.nb1; b += bs) {
-        p.hist1[(uint64_t)b * p.nct + c.fci] = s_h1[b];
-        s_h1[b] = 0;
+        uint32_t sum = 0;
+        for (uint32_t w = 0; w < nwaves; w++) {
+          sum += s_h1w[w * p.nb1 + b];
+          s_h1w[w * p.nb1 + b] = 0;
+        }
+        p.hist1[(uint64_t)c.fci * p.nb1 + b] = sum;
       }
       __syncthreads();
     }
@@ -264,6 +346,7 @@ size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
   if (mode == MODE_FILTERED) b += (size_t)p.filt_words * 4;
   b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
   b += 256;
+  b += (size_t)p.hist_words * 4;
   return b;
 }
 

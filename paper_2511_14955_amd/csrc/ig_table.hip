@@ -22,20 +22,15 @@
 
 namespace ig {
 
-__global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint64_t *mlo,
-                             uint64_t *mhi, uint32_t *mval, uint64_t mmask) {
+// Slot: rank+1 in the low rank_bits bits, a fingerprint of the key's hash above them.
+__global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *map,
+                             uint64_t mmask, uint32_t rank_bits) {
   const uint64_t kept = *kept_p;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t lo = tlo[i], hi = thi[i];
-    uint64_t slot = hash_key(lo, hi) & mmask;
-    for (;;) {
-      if (atomicCAS(mval + slot, 0u, (uint32_t)(i + 1)) == 0u) {
-        mlo[slot] = lo;
-        mhi[slot] = hi;
-        break;
-      }
-      slot = (slot + 1) & mmask;
-    }
+    const uint64_t h = hash_key(tlo[i], thi[i]);
+    const uint32_t v = (uint32_t)(i + 1) | (rank_bits >= 32 ? 0u : (map_fp(h, rank_bits) << rank_bits));
+    uint64_t slot = h & mmask;
+    while (atomicCAS(map + slot, 0u, v) != 0u) slot = (slot + 1) & mmask;
   }
 }
 
@@ -72,10 +67,11 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     if (w > maxw) w = maxw;
     words = (uint32_t)w;
   }
-  if (dev_reserve(c, ts.map_lo, cap * 8) || dev_reserve(c, ts.map_hi, cap * 8) || dev_reserve(c, ts.map_val, cap * 4) ||
-      dev_reserve(c, ts.filt, (uint64_t)words * 4))
-    return IG_ENOMEM;
+  if (dev_reserve(c, ts.map, cap * 4) || dev_reserve(c, ts.filt, (uint64_t)words * 4)) return IG_ENOMEM;
   ts.map_mask = cap - 1;
+  uint32_t rb = 1;
+  while (rb < 32 && (1ull << rb) <= k_max) rb++;   // rank+1 <= k_max fits
+  ts.rank_bits = rb;
   ts.filt_words = words;
   ts.filt_kind = kind;
   return IG_OK;
@@ -83,15 +79,15 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
 
 hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned long long *kept_dev) {
   hipStream_t s = c->stream;
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask + 1, 0, s);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.map.p), ts.map_mask + 1, 0, s);
   if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.filt.p), ts.filt_words, 0, s);
   if (e != hipSuccess) return e;
   uint64_t g = (k_max + 255) / 256;
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
-                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint64_t *>(ts.map_lo.p),
-                     reinterpret_cast<uint64_t *>(ts.map_hi.p), reinterpret_cast<uint32_t *>(ts.map_val.p), ts.map_mask);
+                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.map.p),
+                     ts.map_mask, ts.rank_bits);
   hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
                      reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.filt.p),
                      ts.filt_words, ts.filt_kind);
@@ -107,9 +103,10 @@ struct FeatParams {
   uint32_t n;
   const uint32_t *filt;
   uint32_t filt_words, filt_kind;
-  const uint64_t *mkey_lo, *mkey_hi;
-  const uint32_t *mval;
+  const uint32_t *map;
   uint64_t mmask;
+  uint32_t rank_bits;
+  const uint64_t *tkeys_lo, *tkeys_hi;
   uint32_t *bitmaps;
   uint32_t words;        // per-sequence bitmap words (ceil(kept / 32))
   uint32_t lds_bitmap;   // the bitmap fits in LDS
@@ -174,10 +171,15 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
           }
           uint64_t slot = h & p.mmask;
           int64_t r = -1;
+          const uint32_t fp = map_fp(h, p.rank_bits);
+          const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
           for (;;) {
-            const uint32_t v = p.mval[slot];
+            const uint32_t v = p.map[slot];
             if (!v) break;
-            if (p.mkey_lo[slot] == klo && p.mkey_hi[slot] == khi) { r = (int64_t)v - 1; break; }
+            if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
+              const uint32_t rr = (v & rmask) - 1;
+              if (p.tkeys_lo[rr] == klo && p.tkeys_hi[rr] == khi) { r = rr; break; }
+            }
             slot = (slot + 1) & p.mmask;
           }
           if (r < 0) continue;
@@ -208,10 +210,11 @@ hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s) {
   p.filt = reinterpret_cast<const uint32_t *>(ts.filt.p);
   p.filt_words = ts.filt_words;
   p.filt_kind = ts.filt_kind;
-  p.mkey_lo = reinterpret_cast<const uint64_t *>(ts.map_lo.p);
-  p.mkey_hi = reinterpret_cast<const uint64_t *>(ts.map_hi.p);
-  p.mval = reinterpret_cast<const uint32_t *>(ts.map_val.p);
+  p.map = reinterpret_cast<const uint32_t *>(ts.map.p);
   p.mmask = ts.map_mask;
+  p.rank_bits = ts.rank_bits;
+  p.tkeys_lo = reinterpret_cast<const uint64_t *>(ts.lo.p);
+  p.tkeys_hi = reinterpret_cast<const uint64_t *>(ts.hi.p);
   p.bitmaps = fb.bitmaps;
   p.words = fb.words;
   const uint32_t bits = c->cfg.symbol_bits;
