@@ -36,8 +36,15 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
 }
+// Hash of an n-gram key (lo, hi): xor-shift, one 64-bit multiply, xor-shift (the first half of
+// the murmur3 finalizer).  Keys of at most 64 bits have hi = 0, and the hi term folds away.
+// The filter image takes its word from the high half and its bits from the low bits, map
+// slots take the low bits and fingerprints the top bits.
 __host__ __device__ __forceinline__ uint64_t hash_key(uint64_t lo, uint64_t hi) {
-  return mix64(lo ^ mix64(hi ^ 0x9E3779B97F4A7C15ull));
+  uint64_t x = lo ^ (hi * 0x9E3779B97F4A7C15ull);
+  x ^= x >> 33;
+  x *= 0xFF51AFD7ED558CCDull;
+  return x ^ (x >> 29);
 }
 __host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;

@@ -181,7 +181,9 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       reinterpret_cast<u32x4_t *>(s_stage)[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(src) + i);
     __syncthreads();
 
-    const uint32_t per = (uint32_t)((nwin + bs - 1) / bs);
+    // each thread rolls its key over a contiguous run of windows; an odd run length puts
+    // neighbouring lanes' staged symbols in different LDS banks
+    const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;
     const uint64_t t_lo = (uint64_t)tid * per;
     const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
     if (t_lo < t_hi) {
@@ -209,16 +211,12 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         constexpr int RB = 8;
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
         for (uint64_t t0 = t_lo; t0 < t_hi; t0 += RB) {
+          // q_*[u] are only read where bit u of `live` (or `hit`) is set
           uint64_t q_lo[RB], q_hi[RB], q_klo[RB], q_khi[RB], q_slot[RB];
           uint32_t q_v[RB], q_fp[RB], q_code[RB];
           uint32_t live = 0, hit = 0;
 #pragma unroll
           for (int u = 0; u < RB; u++) {
-            q_v[u] = 0;
-            q_fp[u] = 0;
-            q_lo[u] = q_hi[u] = q_klo[u] = q_khi[u] = 0;
-            q_slot[u] = 0;
-            q_code[u] = 0;
             if (t0 + u >= t_hi) continue;
             const uint64_t g = wbeg + t0 + u;
             k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);

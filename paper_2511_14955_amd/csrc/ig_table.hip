@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
       const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
       for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs) reinterpret_cast<uint4 *>(s_stage)[i] = src[i];
       __syncthreads();
-      const uint32_t per = (uint32_t)((nwin + bs - 1) / bs);
+      const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;   // odd: lanes in different LDS banks
       const uint64_t t_lo = (uint64_t)tid * per, t_hi = t_lo + per < nwin ? t_lo + per : nwin;
       if (t_lo < t_hi) {
         uint64_t klo = 0, khi = 0;
