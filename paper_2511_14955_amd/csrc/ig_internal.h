@@ -198,8 +198,8 @@ struct TableSet {
 };
 
 struct LaunchCfg {
-  uint32_t chunk_syms = 16384;
-  uint32_t block = 512;
+  uint32_t chunk_syms = 23552;       // 23 x 1024: per-thread runs of 23 windows (batches of 8, 8, 7)
+  uint32_t block = 1024;
   uint32_t grid_per_cu = 1;
   uint32_t set_cap = 8192;
   uint32_t filt_max_words = 16384;   // 64 KB of LDS

@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         // first map slot of each survivor is read; then the keys of fingerprint matches are
         // read from the table; then the probes are resolved.  Up to RB independent reads
         // per thread are in flight at each step.
-        constexpr int RB = 8;
+        constexpr int RB = KW == 2 ? 4 : 8;   // 128-bit keys: half the batch, no register spills
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
         for (uint64_t t0 = t_lo; t0 < t_hi; t0 += RB) {
           // q_*[u] are only read where bit u of `live` (or `hit`) is set
