@@ -52,6 +52,31 @@ def profiled_traffic(n, launch):
     return None, None
 
 
+def recall_sample(ig, n, k_keep, files, threads):
+    """Recall of the Intergrams top-k against the exact top-k (Eq. 2, same tie order) on the
+    first `files` files: the exact table is one unfiltered pass at n on a fresh context."""
+    import gen
+    import numpy as np
+    corpus = gen.workload(2, m=files, nthreads=threads)
+    g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
+    g.load(corpus)
+    for j in range(1, n + 1):
+        g.pass_(j, k_keep)
+    approx = g.topk()[0]
+    g.close()
+    e = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
+    e.load(corpus)
+    e.pass_(n, k_keep)   # first pass after a load: every n-gram is counted
+    exact = e.topk()[0]
+    e.close()
+    a = {(int(x), int(y)) for x, y in approx}
+    b = {(int(x), int(y)) for x, y in exact}
+    inter = len(a & b)
+    return {"recall": round(inter / max(1, len(b)), 6), "jaccard": round(inter / max(1, len(a | b)), 6),
+            "k": len(b), "sample": "first %d files (%d bytes), chain n=1..%d vs one unfiltered pass at n=%d" % (
+                files, corpus.nbytes, n, n)}
+
+
 def cpu_baseline(n, k_keep, sample_files, threads):
     """The CPU oracle as it stands, on the first sample_files files of the same corpus."""
     import gen
@@ -136,6 +161,7 @@ def main():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only stream BYTES through a plain device copy kernel 5 times (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=4000, help="requests replayed from the stream (0: skip)")
+    ap.add_argument("--recall-files", type=int, default=1024, help="files of the recall sample (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving HBM budget in bytes")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=64)
@@ -237,6 +263,10 @@ def main():
         gp.close()
     g_launch = g.launch()
     g.close()
+    quality = None
+    if a.recall_files:
+        quality = recall_sample(ig, a.n, a.k, a.recall_files, threads)
+        log("recall: %s" % quality)
 
     out = {
         "metric": "input GB/s per Intergrams pass (n=8,k=1e5) + %HBM roofline; p50/p99 featurize ms",
@@ -251,6 +281,7 @@ def main():
                      "kernel": "k_scan (scan of pass n=%d)" % a.n, "algo_bytes_per_launch": algo_bytes,
                      "avg_launch_ms": round(scan_avg, 4)},
         "serving": serving,
+        "quality": quality,
         "extra": extra,
     }
     lc = g_launch
