@@ -77,7 +77,6 @@ typedef struct {
 #define IG_FLAG_NO_GRAPH      1u  /* launch pass kernels directly instead of a captured hipGraph */
 #define IG_FLAG_PER_FILE      2u  /* one scan launch per file (comparison form) instead of one
                                      persistent launch over the whole work queue */
-#define IG_FLAG_NO_AUTOTUNE   4u  /* use the built-in launch parameters */
 
 /* Fill *cfg with defaults: bytes, Eq. 2, 64-bit counts, device 0, own stream, no budget. */
 void ig_config_default(ig_config *cfg);

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ig.h")
 
 IG_OK, IG_EINVAL, IG_ESTATE, IG_ENOMEM, IG_ETRUNC, IG_EOVERFLOW, IG_EDEVICE, IG_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 FREQ_DOC, FREQ_OCC = 0, 1
-FLAG_NO_GRAPH, FLAG_PER_FILE, FLAG_NO_AUTOTUNE = 1, 2, 4
+FLAG_NO_GRAPH, FLAG_PER_FILE = 1, 2
 REQ_FEATURIZE, REQ_COUNT = 0, 1
 
 _ERRNAMES = {IG_EINVAL: "IG_EINVAL", IG_ESTATE: "IG_ESTATE", IG_ENOMEM: "IG_ENOMEM", IG_ETRUNC: "IG_ETRUNC",

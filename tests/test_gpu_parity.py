@@ -166,3 +166,27 @@ def test_errors_and_state():
     assert g.try_pass(4, 5) == ig.IG_ESTATE
     assert g.try_pass(3, 5) == 0
     assert g.table_info() == (3, 4)
+
+
+def test_hbm_budget():
+    """The context's HBM budget: loads and passes that would exceed it fail with IG_ENOMEM
+    and leave the chain as it was; a sufficient budget gives the same table as none."""
+    corpus = gen.workload(1)   # 4 MiB
+    say("HBM budget: 1 MiB (the corpus does not fit), 12 MiB (a pass does not), unlimited vs 256 MiB")
+    g = ig.Intergrams(hbm_budget=1 << 20)
+    with pytest.raises(ig.IGError) as e:
+        g.load(corpus)
+    assert e.value.code == ig.IG_ENOMEM
+    g.close()
+    g = ig.Intergrams(hbm_budget=12 << 20)
+    g.load(corpus)
+    assert g.try_pass(1, 1000) == ig.IG_ENOMEM
+    assert g.table_info() == (0, 0)
+    with pytest.raises(ig.IGError) as e:
+        g.topk()
+    assert e.value.code == ig.IG_ESTATE
+    g.close()
+    exp, _ = gpu_tables(corpus, [1, 2, 3, 4], 1000)
+    got, gb = gpu_tables(corpus, [1, 2, 3, 4], 1000, ctx=ig.Intergrams(hbm_budget=256 << 20))
+    assert_tables_equal(got, exp, "budget")
+    gb.close()
