@@ -86,6 +86,7 @@ enum FilterKind { FILT_NONE = 0, FILT_DIRECT = 1, FILT_BLOOM = 2 };
 enum StatusBits { ST_TABLE_OVF = 2u, ST_REC_OVF = 4u };
 
 static constexpr uint32_t LDS_EMPTY = 0xFFFFFFFFu;
+static constexpr uint32_t SCAN_QCAP = 128;   // filter survivors queued per wavefront (power of two, >= 127)
 
 // Parameters of one scan (ingest + prefix filter + per-sequence dedup + count) launch.
 struct ScanParams {
@@ -125,6 +126,7 @@ struct ScanParams {
   uint32_t *status;
   uint32_t set_cap;              // LDS de-duplication set entries (power of two)
   uint32_t stage_bytes;          // LDS staging bytes
+  uint32_t qbytes;               // LDS bytes of the per-wavefront survivor rings (filtered 64-bit keys)
 };
 
 // Once-per-sequence counting from chunk records (see ig_dedup.hip).

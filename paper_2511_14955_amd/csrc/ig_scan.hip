@@ -106,7 +106,9 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
   // Eq. 2: histogram of this chunk's records over the level-1 buckets, one copy per
   // wavefront (a few hot buckets take most records; a shared copy would serialize them)
-  uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256);
+  // filtered 64-bit keys: one ring of SCAN_QCAP filter survivors per wavefront
+  uint64_t *s_q = reinterpret_cast<uint64_t *>(s_code + 256);
+  uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256 + p.qbytes);
   __shared__ uint32_t s_chunk;
 
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
@@ -186,23 +188,94 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;
     const uint64_t t_lo = (uint64_t)tid * per;
     const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
-    if (t_lo < t_hi) {
+    const uint64_t sbase = a0;
+    // one surviving candidate: de-duplicate in the chunk's LDS set
+    auto handle = [&](uint32_t cid) {
+      uint32_t slot;
+      const int ins = lds_insert(s_set, capmask, cid, &slot);
+      if (OCC) {
+        if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
+        else cnt_add<CT>(p.cnt, cid, (CT)1);
+      } else if (ins < 0) {
+        emit(wbeg, cid);
+      }
+    };
+    if (MODE == MODE_FILTERED && KW == 1 && p.qbytes) {
+      // About a third of the windows pass the filter, so nearly every wavefront has a
+      // survivor at each step: resolving survivors in place would run the probe on all 64
+      // lanes for a few live ones.  Survivors' keys are compacted into the wavefront's
+      // LDS ring instead (ballot + prefix count) and resolved 64 at a time, one per lane.
+      constexpr int RBC = 4;
+      uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
+      const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
+      uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
+      KeyT<1> k;
+      k.clear();
+      if (t_lo < t_hi)
+        for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, wbeg + t_lo + r, sbase), mlo, mhi);
+      // exact rank of each queued key's prefix (map slot, fingerprint, then the table's key)
+      auto drain = [&](uint32_t cnt) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (lane < cnt) {
+          const uint64_t key = q[(head + lane) & (SCAN_QCAP - 1)];
+          const uint64_t plo = key >> B;
+          const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
+          const uint64_t h = hash_key(plo, 0);
+          const uint32_t fp = map_fp(h, p.rank_bits);
+          uint64_t slot = h & p.mmask;
+          uint32_t v = p.map[slot];
+          while (v != 0) {
+            if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
+              const uint32_t r = (v & rmask) - 1;
+              if (p.tkeys_lo[r] == plo) {
+                handle(r * p.sigma + code);
+                break;
+              }
+            }
+            slot = (slot + 1) & p.mmask;
+            v = p.map[slot];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        head += cnt;
+      };
+      // the trip count is the same for all threads (per), so every lane takes part in the ballots
+      for (uint32_t it = 0; it < per; it += RBC) {
+        uint64_t kk[RBC];
+        uint32_t pass = 0;
+#pragma unroll
+        for (int u = 0; u < RBC; u++) {
+          const uint64_t t = t_lo + it + u;
+          if (t >= t_hi) continue;
+          k.template push<B>(stage_sym<B>(s_stage, wbeg + t + n - 1, sbase), mlo, mhi);
+          kk[u] = k.lo;
+          const uint64_t plo = k.lo >> B;
+          bool ok = true;
+          if (p.filt_kind == FILT_DIRECT) {
+            ok = (s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u;
+          } else if (p.filt_kind == FILT_BLOOM) {
+            const uint64_t h = hash_key(plo, 0);
+            const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
+            const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+            ok = (w & bm) == bm;
+          }
+          pass |= (uint32_t)ok << u;
+        }
+#pragma unroll
+        for (int u = 0; u < RBC; u++) {
+          const bool sv = (pass >> u) & 1u;
+          const uint64_t m = __ballot(sv);
+          if (sv) q[(tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1)] = kk[u];
+          tail += (uint32_t)__popcll(m);
+          if (tail - head >= 64) drain(64);
+        }
+      }
+      if (tail != head) drain(tail - head);
+    } else if (t_lo < t_hi) {
       KeyT<KW> k;
       k.clear();
       const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
-      const uint64_t sbase = (B == 8) ? a0 : a0;
       for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
-      // one surviving candidate: de-duplicate in the chunk's LDS set
-      auto handle = [&](uint32_t cid) {
-        uint32_t slot;
-        const int ins = lds_insert(s_set, capmask, cid, &slot);
-        if (OCC) {
-          if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
-          else cnt_add<CT>(p.cnt, cid, (CT)1);
-        } else if (ins < 0) {
-          emit(wbeg, cid);
-        }
-      };
       if (MODE == MODE_FILTERED) {
         // Windows are taken RB at a time: every window's key is rolled and filtered and the
         // first map slot of each survivor is read; then the keys of fingerprint matches are
@@ -344,6 +417,7 @@ size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
   if (mode == MODE_FILTERED) b += (size_t)p.filt_words * 4;
   b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
   b += 256;
+  b += p.qbytes;
   b += (size_t)p.hist_words * 4;
   return b;
 }
