@@ -365,8 +365,14 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // the LDS check assumes the largest level-1 histogram (256 buckets per wavefront)
   p.hist_words = occ ? 0u : (c->lc.block / 64) * 256u;
   p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 8u : 0u;
-  // without LDS for the survivor rings the scan resolves survivors in place
+  // without LDS for the survivor rings the scan resolves survivors in place; so it does when
+  // the previous table holds every (n-1)-gram over the alphabet (every window survives)
   if (p.qbytes && scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192) p.qbytes = 0;
+  if (p.qbytes) {
+    uint64_t space = 1;
+    for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
+    if (space <= c->kept) p.qbytes = 0;
+  }
   if (scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
                      (unsigned long long)scan_lds_bytes(p, mode, occ));

@@ -95,7 +95,8 @@ __device__ __forceinline__ uint32_t stage_sym(const uint8_t *s_stage, uint64_t g
   return (byte >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
 }
 
-template <int B, int KW, int MODE, int OCC, typename CT>
+// CMP: filter survivors are compacted into per-wavefront rings (filtered 64-bit keys only)
+template <int B, int KW, int MODE, int OCC, typename CT, int CMP>
 __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         emit(wbeg, cid);
       }
     };
-    if (MODE == MODE_FILTERED && KW == 1 && p.qbytes) {
+    if constexpr (CMP != 0) {
       // About a third of the windows pass the filter, so nearly every wavefront has a
       // survivor at each step: resolving survivors in place would run the probe on all 64
       // lanes for a few live ones.  Survivors' keys are compacted into the wavefront's
@@ -219,11 +220,11 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         if (lane < cnt) {
           const uint64_t key = q[(head + lane) & (SCAN_QCAP - 1)];
           const uint64_t plo = key >> B;
-          const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
           const uint64_t h = hash_key(plo, 0);
           const uint32_t fp = map_fp(h, p.rank_bits);
           uint64_t slot = h & p.mmask;
           uint32_t v = p.map[slot];
+          const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
           while (v != 0) {
             if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
               const uint32_t r = (v & rmask) - 1;
@@ -240,34 +241,50 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         head += cnt;
       };
       // the trip count is the same for all threads (per), so every lane takes part in the ballots
+      const bool bloom = p.filt_kind == FILT_BLOOM, direct = p.filt_kind == FILT_DIRECT;
       for (uint32_t it = 0; it < per; it += RBC) {
+        // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
+        // each issued together: lanes past their last window read a staged symbol in range
+        // and never pass
         uint64_t kk[RBC];
+        uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
         uint32_t pass = 0;
 #pragma unroll
         for (int u = 0; u < RBC; u++) {
           const uint64_t t = t_lo + it + u;
-          if (t >= t_hi) continue;
-          k.template push<B>(stage_sym<B>(s_stage, wbeg + t + n - 1, sbase), mlo, mhi);
-          kk[u] = k.lo;
-          const uint64_t plo = k.lo >> B;
-          bool ok = true;
-          if (p.filt_kind == FILT_DIRECT) {
-            ok = (s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u;
-          } else if (p.filt_kind == FILT_BLOOM) {
-            const uint64_t h = hash_key(plo, 0);
-            const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
-            const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
-            ok = (w & bm) == bm;
-          }
-          pass |= (uint32_t)ok << u;
+          sym[u] = stage_sym<B>(s_stage, wbeg + (t < nwin ? t : nwin - 1) + n - 1, sbase);
         }
 #pragma unroll
         for (int u = 0; u < RBC; u++) {
-          const bool sv = (pass >> u) & 1u;
+          k.template push<B>(sym[u], mlo, mhi);
+          kk[u] = k.lo;
+          const uint64_t plo = k.lo >> B;
+          if (bloom) {
+            const uint64_t h = hash_key(plo, 0);
+            widx[u] = (uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32);
+            bm[u] = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+          } else {
+            widx[u] = direct ? (uint32_t)(plo >> 5) & fmask : 0u;
+            bm[u] = direct ? 1u << (plo & 31) : 0u;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
+#pragma unroll
+        for (int u = 0; u < RBC; u++)
+          pass |= (uint32_t)((w[u] & bm[u]) == bm[u] && t_lo + it + u < t_hi) << u;
+        // a rolled loop (the keys shift down one register per step) keeps a single copy of
+        // the drain in the loop body
+#pragma unroll 1
+        for (int u = 0; u < RBC; u++) {
+          const bool sv = pass & 1u;
           const uint64_t m = __ballot(sv);
-          if (sv) q[(tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1)] = kk[u];
+          if (sv) q[(tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1)] = kk[0];
           tail += (uint32_t)__popcll(m);
           if (tail - head >= 64) drain(64);
+          pass >>= 1;
+#pragma unroll
+          for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
         }
       }
       if (tail != head) drain(tail - head);
@@ -425,12 +442,18 @@ size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
 template <int B, int KW, int MODE, int OCC, typename CT>
 static hipError_t launch_t(const ScanParams &p, uint32_t grid, uint32_t block, hipStream_t s) {
   const size_t lds = scan_lds_bytes(p, MODE, OCC);
-  auto fn = k_scan<B, KW, MODE, OCC, CT>;
+  constexpr int can_cmp = (MODE == MODE_FILTERED && KW == 1) ? 1 : 0;
+  auto fn0 = k_scan<B, KW, MODE, OCC, CT, 0>;
+  auto fn1 = k_scan<B, KW, MODE, OCC, CT, can_cmp>;
   if (grid == 0) {   // preparation call: allow the whole LDS of a CU (never issued during a capture)
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               160 * 1024 - 4096);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 4096);
+    if (e == hipSuccess && can_cmp)
+      e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn1), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024 - 4096);
+    return e;
   }
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, p);
+  hipLaunchKernelGGL((can_cmp && p.qbytes) ? fn1 : fn0, dim3(grid), dim3(block), lds, s, p);
   return hipGetLastError();
 }
 
