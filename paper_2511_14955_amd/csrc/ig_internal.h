@@ -46,6 +46,22 @@ __host__ __device__ __forceinline__ uint64_t hash_key(uint64_t lo, uint64_t hi) 
   x *= 0xFF51AFD7ED558CCDull;
   return x ^ (x >> 29);
 }
+// Quotient map over keys of w <= 64 bits.  qmix is a bijection of w-bit values (xor-shifts and
+// odd multiplies modulo 2^w); the top sbits of the mix choose the home slot and the low qbits are
+// stored in the slot, above the displacement from home (dbits) and rank+1 (rbits).  A slot's
+// home and stored bits give back the whole mix, hence the key: one 8-byte read identifies it.
+struct QMapShape {
+  uint32_t w, sbits, qbits, rbits, dbits;
+};
+__host__ __device__ __forceinline__ uint64_t qmix(uint64_t x, uint32_t w) {
+  const uint64_t m = w >= 64 ? ~0ull : ((1ull << w) - 1);
+  const uint32_t s = (w + 1) >> 1;
+  x ^= x >> s;
+  x = (x * 0xFF51AFD7ED558CCDull) & m;
+  x ^= x >> s;
+  x = (x * 0xC4CEB9FE1A85EC53ull) & m;
+  return x ^ (x >> s);
+}
 __host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
   return x;
@@ -109,6 +125,10 @@ struct ScanParams {
   uint64_t mmask;
   uint32_t rank_bits;            // low bits of a slot holding rank+1
   const uint64_t *tkeys_lo, *tkeys_hi;   // previous table's keys, in rank order
+  const uint64_t *qmap;          // quotient map of the previous table (null: none)
+  const uint32_t *qflag;         // non-zero: a key of that table did not fit its displacement field (lookups
+                                 // then use the fingerprinted map and the table's keys)
+  QMapShape qs;
   // large unfiltered passes: key table
   uint64_t *tkey_lo, *tkey_hi;
   uint32_t *tstate;
@@ -194,9 +214,12 @@ struct DevBuf {
 struct TableSet {
   DevBuf lo, hi, cnt;
   DevBuf map, filt;               // map: 32-bit fingerprinted slots (rank+1 in the low rank_bits)
+  DevBuf qmap, qflag;             // quotient map (keys of at most 64 bits) and its overflow flag
   uint64_t kept = 0, map_mask = 0;
   uint32_t rank_bits = 32;
   uint32_t n = 0, filt_words = 0, filt_kind = 0;
+  bool has_qmap = false;
+  QMapShape qs{};
 };
 
 struct LaunchCfg {

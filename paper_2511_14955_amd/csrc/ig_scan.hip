@@ -214,33 +214,57 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       k.clear();
       if (t_lo < t_hi)
         for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, wbeg + t_lo + r, sbase), mlo, mhi);
-      // exact rank of each queued key's prefix (map slot, fingerprint, then the table's key)
+      // Exact rank of each queued key's prefix.  With the quotient map one 8-byte slot read
+      // decides (home and stored bits give back the key); otherwise the fingerprinted map and
+      // the table's keys are probed.  An empty slot ends either probe.
+      const bool useq = p.qmap != nullptr && *p.qflag == 0u;
       auto drain = [&](uint32_t cnt) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         if (lane < cnt) {
           const uint64_t key = q[(head + lane) & (SCAN_QCAP - 1)];
           const uint64_t plo = key >> B;
-          const uint64_t h = hash_key(plo, 0);
-          const uint32_t fp = map_fp(h, p.rank_bits);
-          uint64_t slot = h & p.mmask;
-          uint32_t v = p.map[slot];
-          const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
-          while (v != 0) {
-            if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
-              const uint32_t r = (v & rmask) - 1;
-              if (p.tkeys_lo[r] == plo) {
-                handle(r * p.sigma + code);
+          uint32_t cid = LDS_EMPTY;   // not found
+          if (useq) {
+            const uint64_t x = qmix(plo, p.qs.w);
+            uint64_t slot = x >> p.qs.qbits;
+            const uint64_t rem = p.qs.qbits ? (x & ((1ull << p.qs.qbits) - 1)) : 0ull;
+            uint64_t e = p.qmap[slot];
+            const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
+            const uint64_t dmax = (1ull << p.qs.dbits) - 1;
+            const uint32_t rsh = p.qs.rbits + p.qs.dbits;
+            for (uint64_t d = 0; e != 0;) {
+              if (((e >> p.qs.rbits) & dmax) == d && (e >> rsh) == rem) {
+                cid = (((uint32_t)e & rmask) - 1) * p.sigma + code;
                 break;
               }
+              if (++d > dmax) break;
+              slot = (slot + 1) & p.mmask;
+              e = p.qmap[slot];
             }
-            slot = (slot + 1) & p.mmask;
-            v = p.map[slot];
+          } else {
+            const uint64_t h = hash_key(plo, 0);
+            const uint32_t fp = map_fp(h, p.rank_bits);
+            uint64_t slot = h & p.mmask;
+            uint32_t v = p.map[slot];
+            const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
+            while (v != 0) {
+              if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
+                const uint32_t r = (v & rmask) - 1;
+                if (p.tkeys_lo[r] == plo) {
+                  cid = r * p.sigma + code;
+                  break;
+                }
+              }
+              slot = (slot + 1) & p.mmask;
+              v = p.map[slot];
+            }
           }
+          // one insert per lane after the probe, not one per probe step
+          if (cid != LDS_EMPTY) handle(cid);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         head += cnt;
       };
-      // the trip count is the same for all threads (per), so every lane takes part in the ballots
       const bool bloom = p.filt_kind == FILT_BLOOM, direct = p.filt_kind == FILT_DIRECT;
       for (uint32_t it = 0; it < per; it += RBC) {
         // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are

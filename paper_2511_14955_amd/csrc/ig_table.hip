@@ -34,6 +34,30 @@ __global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, const uns
   }
 }
 
+// Quotient map insert of ranks [r0, min(r1, kept)): linear probing from the home slot.  The
+// ranks go in by increasing batches, so that the most frequent keys, which take most lookups,
+// find their home slot free.  A key whose displacement would not fit its field raises the
+// table's flag (lookups then use the fingerprinted map and the table's keys).
+__global__ void k_qmap_insert(const uint64_t *tlo, const unsigned long long *kept_p, uint64_t r0, uint64_t r1,
+                              unsigned long long *qmap, uint32_t *qflag, uint64_t mmask, QMapShape qs) {
+  const uint64_t kept = *kept_p < r1 ? *kept_p : r1;
+  const uint64_t dmax = (1ull << qs.dbits) - 1;
+  for (uint64_t i = r0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t x = qmix(tlo[i], qs.w);
+    uint64_t slot = x >> qs.qbits;
+    const uint64_t rem = qs.qbits ? (x & ((1ull << qs.qbits) - 1)) : 0ull;
+    for (uint64_t d = 0;; d++) {
+      if (d > dmax) {
+        atomicOr(qflag, 1u);
+        break;
+      }
+      const uint64_t e = (rem << (qs.rbits + qs.dbits)) | (d << qs.rbits) | (i + 1);
+      if (atomicCAS(qmap + slot, 0ull, (unsigned long long)e) == 0ull) break;
+      slot = (slot + 1) & mmask;
+    }
+  }
+}
+
 __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *filt,
                                uint32_t words, uint32_t kind) {
   const uint64_t kept = *kept_p;
@@ -67,10 +91,25 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     if (w > maxw) w = maxw;
     words = (uint32_t)w;
   }
-  if (dev_reserve(c, ts.map, cap * 4) || dev_reserve(c, ts.filt, (uint64_t)words * 4)) return IG_ENOMEM;
-  ts.map_mask = cap - 1;
   uint32_t rb = 1;
   while (rb < 32 && (1ull << rb) <= k_max) rb++;   // rank+1 <= k_max fits
+  if (dev_reserve(c, ts.map, cap * 4) || dev_reserve(c, ts.filt, (uint64_t)words * 4)) return IG_ENOMEM;
+  ts.has_qmap = false;
+  if (nbits <= 64) {
+    QMapShape qs{};
+    qs.w = nbits;
+    while ((1ull << qs.sbits) < cap) qs.sbits++;
+    qs.qbits = nbits > qs.sbits ? nbits - qs.sbits : 0;
+    qs.rbits = rb;
+    const int room = 64 - (int)qs.qbits - (int)qs.rbits;
+    if (room >= 6) {
+      qs.dbits = room < 16 ? (uint32_t)room : 16u;
+      if (dev_reserve(c, ts.qmap, cap * 8) || dev_reserve(c, ts.qflag, 64)) return IG_ENOMEM;
+      ts.qs = qs;
+      ts.has_qmap = true;
+    }
+  }
+  ts.map_mask = cap - 1;
   ts.rank_bits = rb;
   ts.filt_words = words;
   ts.filt_kind = kind;
@@ -91,6 +130,21 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
   hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
                      reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.filt.p),
                      ts.filt_words, ts.filt_kind);
+  if (ts.has_qmap) {
+    if ((e = hipGetLastError()) == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t *>(ts.qmap.p), ts.map_mask + 1, 0, s);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.qflag.p), 1, 0, s);
+    if (e != hipSuccess) return e;
+    // ranks [0, 256), [256, 1024), [1024, 4096), ... then the rest
+    uint64_t r0 = 0;
+    for (uint64_t r1 = 256; r0 < k_max; r1 = r1 < (1ull << 14) ? r1 * 4 : k_max) {
+      uint64_t gb = (r1 - r0 + 255) / 256;
+      if (gb > 4096) gb = 4096;
+      hipLaunchKernelGGL(k_qmap_insert, dim3((uint32_t)gb), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
+                         kept_dev, r0, r1, reinterpret_cast<unsigned long long *>(ts.qmap.p),
+                         reinterpret_cast<uint32_t *>(ts.qflag.p), ts.map_mask, ts.qs);
+      r0 = r1;
+    }
+  }
   return hipGetLastError();
 }
 
