@@ -369,7 +369,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
   // the LDS check assumes the largest level-1 histogram (256 buckets per wavefront)
   p.hist_words = occ ? 0u : (c->lc.block / 64) * 256u;
-  p.qbytes = (mode == MODE_FILTERED && kw == 1 && p.qmap) ? (c->lc.block / 64) * SCAN_QCAP * 8u : 0u;
+  p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 8u : 0u;
   // without LDS for the survivor rings the scan resolves survivors in place; so it does when
   // the previous table holds every (n-1)-gram over the alphabet (every window survives)
   if (p.qbytes && scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192) p.qbytes = 0;
