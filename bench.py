@@ -52,29 +52,39 @@ def profiled_traffic(n, launch):
     return None, None
 
 
-def recall_sample(ig, n, k_keep, files, threads):
-    """Recall of the Intergrams top-k against the exact top-k (Eq. 2, same tie order) on the
-    first `files` files: the exact table is one unfiltered pass at n on a fresh context."""
+def recall_sample(ig, n, k_keep, files, threads, zs=(1.0, 1.5, 2.0)):
+    """Recall and Jaccard of the Intergrams top-k against the exact top-k (Eq. 2, same tie
+    order) on the first `files` files: the exact table is one unfiltered pass at n on a fresh
+    context.  Two forms: the chain n = 1..n keeping k_keep at every pass (the timed pass's
+    table), and Algorithm 3 as a whole (dense 3-gram pass, ceil(z*k) kept below n) per z."""
     import gen
-    import numpy as np
     corpus = gen.workload(2, m=files, nthreads=threads)
+    e = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
+    e.load(corpus)
+    e.pass_(n, k_keep)   # first pass after a load: every n-gram is counted
+    exact = {(int(x), int(y)) for x, y in e.topk()[0]}
+    e.close()
+
+    def score(keys):
+        a = {(int(x), int(y)) for x, y in keys}
+        inter = len(a & exact)
+        return round(inter / max(1, len(exact)), 6), round(inter / max(1, len(a | exact)), 6)
+
     g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
     g.load(corpus)
     for j in range(1, n + 1):
         g.pass_(j, k_keep)
-    approx = g.topk()[0]
+    recall, jac = score(g.topk()[0])
+    sched = []
+    for z in zs:
+        g.intergrams(n, k_keep, z)
+        r, jz = score(g.topk()[0])
+        sched.append({"z": z, "recall": r, "jaccard": jz})
     g.close()
-    e = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
-    e.load(corpus)
-    e.pass_(n, k_keep)   # first pass after a load: every n-gram is counted
-    exact = e.topk()[0]
-    e.close()
-    a = {(int(x), int(y)) for x, y in approx}
-    b = {(int(x), int(y)) for x, y in exact}
-    inter = len(a & b)
-    return {"recall": round(inter / max(1, len(b)), 6), "jaccard": round(inter / max(1, len(a | b)), 6),
-            "k": len(b), "sample": "first %d files (%d bytes), chain n=1..%d vs one unfiltered pass at n=%d" % (
-                files, corpus.nbytes, n, n)}
+    return {"recall": recall, "jaccard": jac, "k": len(exact),
+            "sample": "first %d files (%d bytes), chain n=1..%d vs one unfiltered pass at n=%d" % (
+                files, corpus.nbytes, n, n),
+            "algorithm3": sched}
 
 
 def cpu_baseline(n, k_keep, sample_files, threads):

@@ -105,6 +105,17 @@ int  ig_load_batch(ig_ctx *ctx, const void *data, uint64_t data_bytes,
  * IG_ENOMEM, IG_EDEVICE.  On error the previous table is kept. */
 int  ig_pass(ig_ctx *ctx, uint32_t n, uint64_t k_keep);
 
+/* The whole of Algorithm 3 with z-oversampling (Section 4; z as in the evaluation):
+ * the chain run since the last load is discarded, then
+ *  - a fresh, unfiltered pass at n0 = min(n, floor(24 / b)) (3 for bytes: Algorithm 2's
+ *    direct-indexed count over all 2^24 3-grams) keeps ceil(z*k) grams, and
+ *  - the filtered passes j = n0+1 .. n keep ceil(z*k) grams for j < n and k at j = n.
+ * With n <= n0 the single pass at n keeps k.  Afterwards the retained table is the
+ * top-k of the last pass, as after ig_pass(ctx, n, k), and ig_rewind undoes that pass.
+ * Errors: IG_EINVAL (k = 0, z < 1 or not finite, ceil(z*k) >= 2^63, or n as in
+ * ig_pass), then those of ig_pass; on an error the passes that completed remain. */
+int  ig_intergrams(ig_ctx *ctx, uint32_t n, uint64_t k, double z);
+
 /* Undo the last pass: the table retained before it becomes current again
  * (one level; the state right after ig_load_batch counts as a level), so the
  * last pass can be run again.  Device-side pointer swap, no copy.

@@ -7,6 +7,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``brute.py`` is an independent brute force used to pin it.
 """
 import ctypes
+import math
 import os
 import subprocess
 
@@ -93,6 +94,25 @@ class Oracle:
 
     def pass_(self, n, k_keep):
         return int(self._lib.igo_pass(self._h, n, k_keep))
+
+    def intergrams(self, corpus, n, k, z=1.0):
+        """Algorithm 3 as a whole (Section 4), on a freshly loaded ``corpus``.
+
+        P^(n0) is the top ceil(z*k) of all n0-grams (Algorithm 2 for bytes, n0 = 3; for
+        b-bit symbols n0 is the largest length whose keys fit 24 bits, never above n); then
+        for j = n0+1 .. n the j-grams whose (j-1)-prefix is in P^(j-1) are counted and
+        ceil(z*k) are kept while j < n, k at j = n.  Returns the last pass's return code.
+        """
+        if not (z >= 1.0 and math.isfinite(z)) or k < 1 or n < 1:
+            raise ValueError("need n >= 1, k >= 1, finite z >= 1")
+        kz = math.ceil(z * float(k))
+        n0 = min(n, 24 // self.symbol_bits)
+        self.load(corpus)                   # the first pass after a load is unfiltered
+        for j in range(n0, n + 1):
+            rc = self.pass_(j, kz if j < n else k)
+            if rc:
+                return rc
+        return 0
 
     def kept(self):
         return int(self._lib.igo_kept(self._h))

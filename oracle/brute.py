@@ -36,6 +36,19 @@ def brute_pass(files, n, k_keep, prev=None, occ=False):
     return items[:k_keep]
 
 
+def brute_intergrams(files, n, k, z, symbol_bits=8, occ=False):
+    """Algorithm 3 with z-oversampling on symbol strings: the top ceil(z*k) n0-grams
+    (n0 = min(n, 24 // symbol_bits)), then each longer gram length filtered by the
+    previous table, ceil(z*k) kept below n and k at n.  Returns the last table."""
+    import math
+    kz = math.ceil(z * float(k))
+    n0 = min(n, 24 // symbol_bits)
+    table = brute_pass(files, n0, kz if n0 < n else k, occ=occ)
+    for j in range(n0 + 1, n + 1):
+        table = brute_pass(files, j, kz if j < n else k, prev={g for g, _ in table}, occ=occ)
+    return table
+
+
 def brute_chain(files, ns, k_keep, occ=False):
     """Passes over consecutive n (the first one unfiltered); returns one table per n."""
     out, prev = [], None

@@ -107,6 +107,7 @@ def load_library(path=LIB_PATH):
     lib.ig_load_batch.argtypes = [vp, vp, u64, P(u64), u64, i32]
     lib.ig_pass.argtypes = [vp, u32, u64]
     lib.ig_rewind.argtypes = [vp]
+    lib.ig_intergrams.argtypes = [vp, u32, u64, dbl]
     lib.ig_topk.argtypes = [vp, u64, vp, vp, P(u64)]
     lib.ig_table_info.argtypes = [vp, P(u32), P(u64)]
     lib.ig_featurize.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
@@ -188,6 +189,11 @@ class Intergrams:
 
     def pass_(self, n, k_keep):
         return self._check(self._lib.ig_pass(self._h, n, k_keep))
+
+    def intergrams(self, n, k, z=1.0):
+        """Algorithm 3 from a fresh chain: dense pass at min(n, 24 // b), z-oversampled
+        passes up to n - 1 (ceil(z*k) kept), k kept at n."""
+        return self._check(self._lib.ig_intergrams(self._h, n, k, float(z)))
 
     def rewind(self):
         """Make the table retained before the last pass current again."""

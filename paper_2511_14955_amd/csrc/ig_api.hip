@@ -1,5 +1,6 @@
 // C ABI of libintergrams.so: contexts, corpus load, passes, table access, featurize.
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -638,6 +639,33 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   c->kept = kept;
   c->n_prev = n;
   c->fresh = false;
+  return IG_OK;
+}
+
+// Algorithm 3 as a whole: the dense first pass of Algorithm 2 generalized to b-bit symbols
+// (the largest gram length whose keys fit 24 bits), z-oversampled intermediate passes, k at n.
+int ig_intergrams(ig_ctx *c, uint32_t n, uint64_t k, double z) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  const uint32_t b = c->cfg.symbol_bits;
+  if (n == 0 || (uint64_t)n * b > 128 || k == 0) return set_error(c, IG_EINVAL, "bad n=%u or k", n);
+  if (!(z >= 1.0) || !std::isfinite(z)) return set_error(c, IG_EINVAL, "z must be finite and >= 1");
+  const double zk = std::ceil(z * (double)k);
+  if (zk >= 9223372036854775808.0) return set_error(c, IG_EINVAL, "ceil(z*k) too large");
+  if (!c->loaded) return set_error(c, IG_ESTATE, "no corpus loaded");
+  const uint64_t kz = (uint64_t)zk;
+  uint32_t n0 = 24 / b;
+  if (n0 > n) n0 = n;
+  // a fresh chain: the next pass counts every n0-gram
+  c->fresh = true;
+  c->n_prev = 0;
+  c->kept = 0;
+  c->can_rewind = false;
+  for (uint32_t j = n0; j <= n; j++) {
+    const int rc = ig_pass(c, j, j < n ? kz : k);
+    if (rc) return rc;
+  }
   return IG_OK;
 }
 

@@ -124,6 +124,36 @@ def test_fresh_unfiltered_large_n():
     assert_tables_equal(got, exp, "fresh n=40 dna")
 
 
+@pytest.mark.parametrize("workload,m,n,k", [(2, 96, 8, 2000), (3, 200, 12, 5000), (4, 12, 18, 3000)])
+@pytest.mark.parametrize("z", [1.0, 1.5, 2.0])
+def test_intergrams_schedule(workload, m, n, k, z):
+    """Algorithm 3 as a whole (dense first pass, z-oversampled passes, k at n) equals the
+    oracle's schedule; a chain already in progress is discarded first."""
+    import oracle
+    corpus = gen.workload(workload, m=m)
+    say("Algorithm 3 schedule: workload %d first %d sequences, n=%d, k=%d, z=%g" % (workload, m, n, k, z))
+    o = oracle.Oracle(corpus.symbol_bits, oracle.FREQ_DOC, nthreads=min(16, os.cpu_count() or 1))
+    assert o.intergrams(corpus, n, k, z) == 0
+    exp = o.topk()
+    g = ig.Intergrams(symbol_bits=corpus.symbol_bits, freq=ig.FREQ_DOC)
+    try:
+        g.load(corpus)
+        g.pass_(1, 10)
+        g.pass_(2, 10)
+        g.intergrams(n, k, z)
+        assert g.table_info() == (n, len(exp[1]))
+        assert_tables_equal([g.topk()], [exp], "schedule")
+        g.rewind()                      # back to the z-oversampled table at n - 1
+        g.pass_(n, k)
+        assert_tables_equal([g.topk()], [exp], "schedule, last pass again")
+        for bad in (0.5, float("nan"), float("inf")):
+            with pytest.raises(ig.IGError) as e:
+                g.intergrams(n, k, bad)
+            assert e.value.code == ig.IG_EINVAL
+    finally:
+        g.close()
+
+
 def test_edge_cases():
     cases = [
         ("empty corpus", [], [1, 2], 10),

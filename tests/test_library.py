@@ -12,7 +12,7 @@ import paper_2511_14955_amd as ig
 def test_header_declares_the_api():
     names = ig.header_functions()
     for required in ["ig_create", "ig_destroy", "ig_load_batch", "ig_pass", "ig_rewind", "ig_topk", "ig_featurize",
-                     "ig_autotune", "ig_serve_start", "ig_submit", "ig_poll", "ig_serve_stop"]:
+                     "ig_autotune", "ig_serve_start", "ig_submit", "ig_poll", "ig_serve_stop", "ig_intergrams"]:
         assert required in names
 
 

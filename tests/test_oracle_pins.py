@@ -9,6 +9,9 @@
 * Closed forms and invariants: the window count, Lemma 1's exact identity,
   anti-monotonicity, per-sequence bounds, and that a filter holding every
   previous gram is a no-op.
+* Algorithm 3 as a whole (z-oversampled schedule from the dense first pass)
+  against the same schedule over brute-force passes, and, when z*k covers every
+  gram, against the exact top-k.
 """
 import os
 import random
@@ -310,3 +313,45 @@ def test_argument_and_state_errors():
     o2.load(gen.from_files([bytes([0, 1, 2, 3])], 2))
     assert o2.pass_(64, 5) == 0                        # 64 x 2 bits = 128 bits
     assert o2.pass_(65, 5) == oracle.EINVAL
+
+
+# ---------------------------------------------------------------- Algorithm 3 schedule
+
+@pytest.mark.parametrize("bits", [8, 2])
+def test_intergrams_schedule_equals_brute_force(bits):
+    rng = random.Random(77 + bits)
+    nmax = 6 if bits == 8 else 15          # 2-bit symbols: the dense first pass is at 12
+    for trial in range(60):
+        files = random_files(rng, bits)
+        if bits == 2:
+            files = [f + bytes(rng.randrange(4) for _ in range(rng.randint(0, 30))) for f in files]
+        n = rng.randint(1, nmax)
+        k = rng.choice([1, 2, 3, 5, 9, 40])
+        z = rng.choice([1.0, 1.5, 2.0, 3.7])
+        corpus = gen.from_files(files, bits)
+        o = oracle.Oracle(bits, oracle.FREQ_DOC, nthreads=rng.choice([1, 3]))
+        assert o.intergrams(corpus, n, k, z) == 0
+        exp = brute.brute_intergrams(files, n, k, z, symbol_bits=bits)
+        assert as_strings(o.table(), n, bits) == exp, (trial, n, k, z)
+
+
+def test_intergrams_large_z_is_exact():
+    # when ceil(z*k) retains every gram of every intermediate length, nothing is filtered
+    # out, so the schedule returns the exact top-k of all n-grams
+    rng = random.Random(5)
+    for trial in range(30):
+        files = [bytes(rng.randrange(3) for _ in range(rng.randint(0, 40))) for _ in range(rng.randint(1, 8))]
+        n, k = rng.randint(3, 7), rng.choice([1, 4, 10])
+        z = 1e6
+        o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=2)
+        assert o.intergrams(gen.from_files(files), n, k, z) == 0
+        assert as_strings(o.table(), n, 8) == brute.brute_pass(files, n, k), trial
+
+
+def test_intergrams_z_one_is_the_plain_chain():
+    corpus = gen.workload(2, m=24)
+    o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=4)
+    assert o.intergrams(corpus, 6, 700, 1.0) == 0
+    assert o.table() == oracle_chain(corpus, [3, 4, 5, 6], 700)[-1]
+    with pytest.raises(ValueError):
+        o.intergrams(corpus, 6, 700, 0.5)
