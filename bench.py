@@ -251,6 +251,16 @@ def main():
         extra["autotune"] = {"identical_tables": tune["identical"],
                              "candidates": [[c["chunk_syms"], c["block"], c["set_cap"], round(c["pass_ms"], 3)]
                                             for c in tune["candidates"]]}
+    # Figure 1's m x k Boolean matrix of the whole loaded corpus against this pass's table
+    # (device bitmaps, then CSR copied to the host)
+    t1 = time.perf_counter()
+    fip, find = g.featurize_loaded()
+    t2 = time.perf_counter()
+    extra["featurize_corpus"] = {"ms": round((t2 - t1) * 1e3, 3), "GB_per_s": round(corpus.nbytes / (t2 - t1) / 1e9, 3),
+                                 "rows": int(len(fip) - 1), "nnz": int(len(find)),
+                                 "note": "whole loaded corpus, CSR on the host included"}
+    log("featurize whole corpus: %s" % extra["featurize_corpus"])
+    del fip, find
     serving = None
     if a.serve_requests:
         serving = serve_stream(g, ig, a.serve_requests, a.serve_budget, a.serve_streams, a.serve_batch)

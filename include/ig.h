@@ -140,6 +140,13 @@ int  ig_featurize(ig_ctx *ctx, const void *data, uint64_t data_bytes,
                   const uint64_t *sym_offsets, uint64_t m,
                   uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out);
 
+/* The same Boolean rows (Figure 1's m x k matrix) for the m loaded sequences themselves,
+ * from the corpus already resident on the device (no host copy of the data).
+ *  indptr:  host array of m+1 entries; indices: host array of cap entries (may be NULL
+ *  when cap = 0, to learn *nnz_out).  IG_ETRUNC if nnz > cap (indptr is still filled).
+ *  IG_ESTATE before a pass or while serving. */
+int  ig_featurize_loaded(ig_ctx *ctx, uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out);
+
 /* Per-pass measurements of the last ig_pass: device time of the whole pass and of
  * the scan kernel (milliseconds, hipEvent-timed on the context's stream), windows
  * scanned, distinct grams counted, and the scan kernel's average duration. */

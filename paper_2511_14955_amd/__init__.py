@@ -111,6 +111,7 @@ def load_library(path=LIB_PATH):
     lib.ig_topk.argtypes = [vp, u64, vp, vp, P(u64)]
     lib.ig_table_info.argtypes = [vp, P(u32), P(u64)]
     lib.ig_featurize.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
+    lib.ig_featurize_loaded.argtypes = [vp, P(u64), vp, u64, P(u64)]
     lib.ig_last_pass_stats.argtypes = [vp, P(ig_pass_stats)]
     lib.ig_last_error.argtypes = [vp]
     lib.ig_last_error.restype = ctypes.c_char_p
@@ -156,6 +157,7 @@ class Intergrams:
         if rc:
             raise IGError(rc, "ig_create failed")
         self._h = h
+        self._m = 0
         self.symbol_bits = symbol_bits
 
     def close(self):
@@ -186,6 +188,7 @@ class Intergrams:
             data = np.ascontiguousarray(data, np.uint8)
             ptr, nbytes, on_dev = data.ctypes.data, data.nbytes, 0
         self._check(self._lib.ig_load_batch(self._h, ptr, nbytes, _u64p(offs), len(offs) - 1, on_dev))
+        self._m = len(offs) - 1
 
     def pass_(self, n, k_keep):
         return self._check(self._lib.ig_pass(self._h, n, k_keep))
@@ -238,6 +241,19 @@ class Intergrams:
                 continue
             self._check(rc)
             return indptr, ind[:nnz.value]
+
+    def featurize_loaded(self):
+        """CSR rows (indptr uint64[m+1], indices int32[nnz]) of the loaded sequences themselves."""
+        indptr = np.zeros(self._m + 1, np.uint64)
+        nnz = ctypes.c_uint64()
+        # cap 0 sizes the output (indptr and the total are filled, IG_ETRUNC when nnz > 0)
+        rc = self._lib.ig_featurize_loaded(self._h, _u64p(indptr), None, 0, ctypes.byref(nnz))
+        if rc != IG_ETRUNC:
+            self._check(rc)
+        ind = np.zeros(max(int(nnz.value), 1), np.int32)
+        self._check(self._lib.ig_featurize_loaded(self._h, _u64p(indptr), ind.ctypes.data, int(nnz.value),
+                                                  ctypes.byref(nnz)))
+        return indptr, ind[:nnz.value]
 
     def autotune(self, n, k_keep):
         """Search the scan's launch shape on pass n (chain state unchanged); returns a report dict."""

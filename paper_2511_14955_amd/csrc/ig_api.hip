@@ -705,6 +705,54 @@ int ig_topk(ig_ctx *c, uint64_t k, ig_key *keys, uint64_t *counts, uint64_t *k_o
   return IG_OK;
 }
 
+// Boolean rows of a batch already on the device (corpus, offsets, chunks): per-sequence bitmaps
+// of kept ranks, then CSR.
+static int featurize_rows(ig_ctx *c, const FeatBatch &in, uint64_t *indptr, int32_t *indices, uint64_t cap,
+                          uint64_t *nnz_out) {
+  hipStream_t s = c->stream;
+  const uint64_t m = in.m;
+  const uint32_t words = (uint32_t)((c->kept + 31) / 32);
+  DevBuf d_bm, d_nnz, d_ind, d_ptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(s);
+    dev_release(c, d_bm); dev_release(c, d_nnz); dev_release(c, d_ind); dev_release(c, d_ptr);
+  };
+  if (dev_reserve(c, d_bm, std::max<uint64_t>(1, m * words) * 4) || dev_reserve(c, d_nnz, std::max<uint64_t>(1, m) * 8) ||
+      dev_reserve(c, d_ptr, (m + 1) * 8)) {
+    cleanup();
+    return IG_ENOMEM;
+  }
+  FeatBatch fb = in;
+  fb.bitmaps = reinterpret_cast<uint32_t *>(d_bm.p);
+  fb.words = words;
+  hipError_t e = launch_fill_u32(fb.bitmaps, std::max<uint64_t>(1, m * words), 0, s);
+  if (e == hipSuccess && words && fb.nchunks) e = launch_featurize(c, fb, s);
+  if (e == hipSuccess && words)
+    e = launch_rows(fb.bitmaps, m, words, reinterpret_cast<uint64_t *>(d_nnz.p), nullptr, nullptr, 0, 1, s);
+  std::vector<uint64_t> nnz(m, 0);
+  if (e == hipSuccess && m && words) e = hipMemcpyAsync(nnz.data(), d_nnz.p, m * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (check_hip(c, e, "featurize")) { cleanup(); return IG_EDEVICE; }
+  indptr[0] = 0;
+  for (uint64_t i = 0; i < m; i++) indptr[i + 1] = indptr[i] + nnz[i];
+  const uint64_t total = indptr[m];
+  if (nnz_out) *nnz_out = total;
+  if (total > cap) { cleanup(); return set_error(c, IG_ETRUNC, "need %llu indices", (unsigned long long)total); }
+  if (total) {
+    if (!indices) { cleanup(); return set_error(c, IG_EINVAL, "null indices"); }
+    if (dev_reserve(c, d_ind, total * 4)) { cleanup(); return IG_ENOMEM; }
+    e = hipMemcpyAsync(d_ptr.p, indptr, (m + 1) * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = launch_rows(fb.bitmaps, m, words, nullptr, reinterpret_cast<const uint64_t *>(d_ptr.p),
+                      reinterpret_cast<int32_t *>(d_ind.p), total, 0, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(indices, d_ind.p, total * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (check_hip(c, e, "featurize rows")) { cleanup(); return IG_EDEVICE; }
+  }
+  cleanup();
+  return IG_OK;
+}
+
 int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
                  uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
   if (!c) return IG_EINVAL;
@@ -718,7 +766,6 @@ int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_
   const uint64_t need = (sym_offsets[m] * b + 7) / 8;
   if (data_bytes < need || (need && !data)) return set_error(c, IG_EINVAL, "data too small");
   hipStream_t s = c->stream;
-  const uint32_t words = (uint32_t)((c->kept + 31) / 32);
   // chunks of the batch
   std::vector<Chunk> ch;
   const uint64_t CH = c->lc.chunk_syms;
@@ -726,17 +773,14 @@ int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_
     const uint64_t a = sym_offsets[f], L = sym_offsets[f + 1] - a;
     for (uint64_t q = 0; q < L; q += CH) ch.push_back(Chunk{a + q, (uint32_t)f, (uint32_t)std::min<uint64_t>(CH, L - q), L > CH ? 1u : 0u, 0u});
   }
-  DevBuf d_data, d_offs, d_ch, d_bm, d_nnz, d_ind, d_ptr;
+  DevBuf d_data, d_offs, d_ch;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(s);
-    dev_release(c, d_data); dev_release(c, d_offs); dev_release(c, d_ch); dev_release(c, d_bm);
-    dev_release(c, d_nnz); dev_release(c, d_ind); dev_release(c, d_ptr);
+    dev_release(c, d_data); dev_release(c, d_offs); dev_release(c, d_ch);
   };
   const uint64_t alloc = ((need + 15) & ~15ull) + 64;
   if (dev_reserve(c, d_data, alloc) || dev_reserve(c, d_offs, (m + 1) * 8) ||
-      dev_reserve(c, d_ch, std::max<size_t>(1, ch.size()) * sizeof(Chunk)) ||
-      dev_reserve(c, d_bm, std::max<uint64_t>(1, m * words) * 4) || dev_reserve(c, d_nnz, std::max<uint64_t>(1, m) * 8) ||
-      dev_reserve(c, d_ptr, (m + 1) * 8)) {
+      dev_reserve(c, d_ch, std::max<size_t>(1, ch.size()) * sizeof(Chunk))) {
     cleanup();
     return IG_ENOMEM;
   }
@@ -744,33 +788,25 @@ int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_
   if (e == hipSuccess && need) e = hipMemcpyAsync(d_data.p, data, need, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_offs.p, sym_offsets, (m + 1) * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !ch.empty()) e = hipMemcpyAsync(d_ch.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(d_bm.p), std::max<uint64_t>(1, m * words), 0, s);
+  if (check_hip(c, e, "featurize staging")) { cleanup(); return IG_EDEVICE; }
   FeatBatch fb{reinterpret_cast<const uint8_t *>(d_data.p), reinterpret_cast<const uint64_t *>(d_offs.p), m,
-               reinterpret_cast<const Chunk *>(d_ch.p), (uint32_t)ch.size(), reinterpret_cast<uint32_t *>(d_bm.p), words};
-  if (e == hipSuccess && words) e = launch_featurize(c, fb, s);
-  if (e == hipSuccess && words)
-    e = launch_rows(fb.bitmaps, m, words, reinterpret_cast<uint64_t *>(d_nnz.p), nullptr, nullptr, 0, 1, s);
-  std::vector<uint64_t> nnz(m, 0);
-  if (e == hipSuccess && m && words) e = hipMemcpyAsync(nnz.data(), d_nnz.p, m * 8, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (check_hip(c, e, "featurize")) { cleanup(); return IG_EDEVICE; }
-  indptr[0] = 0;
-  for (uint64_t i = 0; i < m; i++) indptr[i + 1] = indptr[i] + nnz[i];
-  const uint64_t total = indptr[m];
-  if (nnz_out) *nnz_out = total;
-  if (total > cap) { cleanup(); return set_error(c, IG_ETRUNC, "need %llu indices", (unsigned long long)total); }
-  if (total) {
-    if (dev_reserve(c, d_ind, total * 4)) { cleanup(); return IG_ENOMEM; }
-    e = hipMemcpyAsync(d_ptr.p, indptr, (m + 1) * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = launch_rows(fb.bitmaps, m, words, nullptr, reinterpret_cast<const uint64_t *>(d_ptr.p),
-                      reinterpret_cast<int32_t *>(d_ind.p), total, 0, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(indices, d_ind.p, total * 4, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (check_hip(c, e, "featurize rows")) { cleanup(); return IG_EDEVICE; }
-  }
+               reinterpret_cast<const Chunk *>(d_ch.p), (uint32_t)ch.size(), nullptr, 0};
+  const int rc = featurize_rows(c, fb, indptr, indices, cap, nnz_out);
   cleanup();
-  return IG_OK;
+  return rc;
+}
+
+int ig_featurize_loaded(ig_ctx *c, uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
+  if (!c) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  if (c->fresh || !c->loaded) return set_error(c, IG_ESTATE, "no pass has run");
+  if (!indptr) return set_error(c, IG_EINVAL, "null indptr");
+  if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
+  // the corpus, its offsets and its chunk list are resident since the load
+  FeatBatch fb{reinterpret_cast<const uint8_t *>(c->data.p), reinterpret_cast<const uint64_t *>(c->offs.p), c->m,
+               reinterpret_cast<const Chunk *>(c->chunks_file.p), (uint32_t)c->nchunks, nullptr, 0};
+  return featurize_rows(c, fb, indptr, indices, cap, nnz_out);
 }
 
 }  // extern "C"

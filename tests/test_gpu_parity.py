@@ -154,6 +154,25 @@ def test_intergrams_schedule(workload, m, n, k, z):
         g.close()
 
 
+@pytest.mark.parametrize("workload,m,ns,k", [(2, 64, list(range(1, 7)), 4000), (4, 10, list(range(1, 15)), 2500)])
+def test_featurize_loaded_corpus(workload, m, ns, k):
+    """Figure 1's m x k Boolean matrix of the loaded sequences themselves equals the oracle's
+    featurization of the same sequences, and the rows of the host-copy entry point."""
+    corpus = gen.workload(workload, m=m)
+    say("featurize the loaded corpus: workload %d first %d sequences, n=%d, k=%d" % (workload, m, ns[-1], k))
+    _, o = oracle_tables(corpus, ns, k)
+    _, g = gpu_tables(corpus, ns, k)
+    try:
+        ip, ind = g.featurize_loaded()
+        eip, eind = o.featurize(corpus)
+        assert np.array_equal(ip, eip) and np.array_equal(ind, eind)
+        hip_, hind = g.featurize(corpus)
+        assert np.array_equal(ip, hip_) and np.array_equal(ind, hind)
+        assert len(ind) > 0
+    finally:
+        g.close()
+
+
 def test_edge_cases():
     cases = [
         ("empty corpus", [], [1, 2], 10),
