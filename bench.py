@@ -11,6 +11,7 @@ Prints one JSON line (see the "roofline" and "cpu_baseline" objects).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -52,13 +53,11 @@ def profiled_traffic(n, launch):
     return None, None
 
 
-def recall_sample(ig, n, k_keep, files, threads, zs=(1.0, 1.5, 2.0)):
+def recall_sample(ig, n, k_keep, corpus, zs=(1.0, 1.5, 2.0)):
     """Recall and Jaccard of the Intergrams top-k against the exact top-k (Eq. 2, same tie
     order) on the first `files` files: the exact table is one unfiltered pass at n on a fresh
     context.  Two forms: the chain n = 1..n keeping k_keep at every pass (the timed pass's
     table), and Algorithm 3 as a whole (dense 3-gram pass, ceil(z*k) kept below n) per z."""
-    import gen
-    corpus = gen.workload(2, m=files, nthreads=threads)
     e = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC)
     e.load(corpus)
     e.pass_(n, k_keep)   # first pass after a load: every n-gram is counted
@@ -83,7 +82,7 @@ def recall_sample(ig, n, k_keep, files, threads, zs=(1.0, 1.5, 2.0)):
     g.close()
     return {"recall": recall, "jaccard": jac, "k": len(exact),
             "sample": "first %d files (%d bytes), chain n=1..%d vs one unfiltered pass at n=%d" % (
-                files, corpus.nbytes, n, n),
+                corpus.m, corpus.nbytes, n, n),
             "algorithm3": sched}
 
 
@@ -284,9 +283,22 @@ def main():
     g_launch = g.launch()
     g.close()
     quality = None
+    theory_rows = None
     if a.recall_files:
-        quality = recall_sample(ig, a.n, a.k, a.recall_files, threads)
+        import gen
+        from paper_2511_14955_amd import theory
+        sample = gen.workload(2, m=a.recall_files, nthreads=threads)
+        quality = recall_sample(ig, a.n, a.k, sample)
         log("recall: %s" % quality)
+        # Section 4.3's quantities per step n -> n+1 on the same sample
+        def fin(v):   # JSON has no NaN or infinity
+            return (round(v, 6) if math.isfinite(v) else None) if isinstance(v, float) else v
+        theory_rows = []
+        for r in theory.diagnostics(ig, sample, list(range(2, a.n)), a.k):
+            theory_rows.append({key: ([{kk: fin(vv) for kk, vv in c.items()} for c in v] if isinstance(v, list) else fin(v))
+                                for key, v in r.items()})
+        log("theory: %s" % theory_rows)
+        del sample
 
     out = {
         "metric": "input GB/s per Intergrams pass (n=8,k=1e5) + %HBM roofline; p50/p99 featurize ms",
@@ -302,6 +314,7 @@ def main():
                      "avg_launch_ms": round(scan_avg, 4)},
         "serving": serving,
         "quality": quality,
+        "theory": theory_rows,
         "extra": extra,
     }
     lc = g_launch
