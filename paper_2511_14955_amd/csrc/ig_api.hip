@@ -459,6 +459,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       dp.seg0 = reinterpret_cast<uint64_t *>(c->seg0.p);
       dp.cnt = c->cnt.p;
       dp.nc = nc;
+      dp.narrow = c->m < 65535 ? 1u : 0u;
       dp.status = reinterpret_cast<uint32_t *>(c->status.p);
       p.rec = reinterpret_cast<uint32_t *>(c->rec0.p);
       p.nrec = reinterpret_cast<uint32_t *>(c->nrec.p);

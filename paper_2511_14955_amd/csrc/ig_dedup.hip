@@ -263,13 +263,21 @@ __global__ void __launch_bounds__(256) k_gather(DedupParams d) {
     }
     __syncthreads();
     const uint32_t *src = d.rec0 + c.s0;
-    for (uint32_t i = tid; i < n; i += 256) {
-      const uint32_t cid = src[i];
-      uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
-      if (b >= d.nb1) b = d.nb1 - 1;   // (only a corrupt record could exceed the candidate space)
-      const uint32_t k = atomicAdd(s_cur + b, 1u);
-      const uint64_t at = s_base[b] + k;
-      if (at < d.cap) out[at] = Rec<R1>::pack(c.file, cid & m1, d.low1);
+    // four records per thread: their loads are issued before the first cursor atomic
+    for (uint32_t i0 = tid; i0 < n; i0 += 4 * 256) {
+      uint32_t cids[4];
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) cids[q] = src[i0 + q * 256 < n ? i0 + q * 256 : n - 1];   // n >= 1
+#pragma unroll
+      for (uint32_t q = 0; q < 4; q++) {
+        if (i0 + q * 256 >= n) break;
+        const uint32_t cid = cids[q];
+        uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
+        if (b >= d.nb1) b = d.nb1 - 1;   // (only a corrupt record could exceed the candidate space)
+        const uint32_t k = atomicAdd(s_cur + b, 1u);
+        const uint64_t at = s_base[b] + k;
+        if (at < d.cap) out[at] = Rec<R1>::pack(c.file, cid & m1, d.low1);
+      }
     }
     __syncthreads();
   }
@@ -448,14 +456,20 @@ __global__ void k_nseg(DedupParams d) {
 }
 
 // One wavefront per segment (segments of one bucket are cut at sequence
-// boundaries); the waves of a workgroup work independently.
-template <typename R2>
-__global__ void __launch_bounds__(256) k_count(DedupParams d) {
+// boundaries); the waves of a workgroup work independently.  Per candidate a wavefront keeps
+// 1 + the sequence of its latest record and its count: 32-bit each, or (NARROW, fewer than
+// 65535 sequences) a 16-bit sequence and a 16-bit count packed two to a word (a count never
+// exceeds the number of sequences, so a half never carries into its neighbour).  Half the LDS
+// per wavefront doubles the wavefronts per CU.
+template <typename R2, int NARROW>
+__global__ void __launch_bounds__(512) k_count(DedupParams d) {
   extern __shared__ __align__(16) uint8_t lds[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const uint32_t cb = 1u << d.low2;
   uint32_t *last = reinterpret_cast<uint32_t *>(lds) + (size_t)wave * 2 * cb;   // 1 + sequence of the latest record
   uint32_t *cnt = last + cb;
+  uint16_t *last16 = reinterpret_cast<uint16_t *>(lds + (size_t)wave * 4 * cb);
+  uint32_t *cnt2 = reinterpret_cast<uint32_t *>(lds + (size_t)wave * 4 * cb + 2 * cb);
   if (rec_overflow(d)) return;
   const R2 *in = reinterpret_cast<const R2 *>(d.l2);
   uint32_t *gcnt = reinterpret_cast<uint32_t *>(d.cnt);
@@ -478,14 +492,27 @@ __global__ void __launch_bounds__(256) k_count(DedupParams d) {
     const uint64_t a = snap_to_sequence(in, lo, hi, lo + size * j / nseg, d.low2);
     const uint64_t b = snap_to_sequence(in, lo, hi, lo + size * (j + 1) / nseg, d.low2);
     if (nseg > 1 && a >= b) continue;   // one sequence spans this cut: the neighbouring segment has it
-    for (uint32_t k = lane; k < cb; k += 64) { last[k] = 0; cnt[k] = 0; }
-    // records of the next round are loaded while this round is processed
-    R2 nxt = 0;
-    if (a + lane < b) nxt = in[a + lane];
-    for (uint64_t s0 = a; s0 < b; s0 += 64) {
+    if (NARROW) {
+      for (uint32_t k = lane; k < cb; k += 64) last16[k] = 0;
+      for (uint32_t k = lane; k < cb / 2; k += 64) cnt2[k] = 0;
+    } else {
+      for (uint32_t k = lane; k < cb; k += 64) { last[k] = 0; cnt[k] = 0; }
+    }
+    // a ring of KR rounds in registers: the loads of the next KR - 1 rounds are in flight while
+    // a round is processed (2 wavefronts per SIMD leave the latency to the wavefront itself)
+    // (loads are unconditional, at an index clamped into the segment: a conditional load would
+    // be waited for where its branch joins)
+    constexpr uint32_t KR = 4;
+    R2 buf[KR];
+#pragma unroll
+    for (uint32_t q = 0; q < KR; q++) buf[q] = in[a + q * 64 + lane < b ? a + q * 64 + lane : b - 1];
+    for (uint64_t s00 = a; s00 < b; s00 += KR * 64) {
+#pragma unroll
+    for (uint32_t q = 0; q < KR; q++) {
+      const uint64_t s0 = s00 + q * 64;   // rounds past b run with every lane invalid
       const bool valid = s0 + lane < b;
-      const R2 r = nxt;
-      if (s0 + 64 + lane < b) nxt = in[s0 + 64 + lane];
+      const R2 r = buf[q];
+      buf[q] = in[s0 + KR * 64 + lane < b ? s0 + KR * 64 + lane : b - 1];
       uint32_t f1 = 0, cl = 0;
       if (valid) {
         f1 = Rec<R2>::file(r, d.low2) + 1;
@@ -496,28 +523,38 @@ __global__ void __launch_bounds__(256) k_count(DedupParams d) {
       const uint64_t below = same & lt;
       const uint32_t pred = below ? 63u - (uint32_t)__clzll((unsigned long long)below) : lane;
       const uint32_t fpred = (uint32_t)__shfl((int)f1, (int)pred);
-      const uint32_t lp = valid ? last[cl] : 0u;
+      const uint32_t lp = valid ? (NARROW ? (uint32_t)last16[cl] : last[cl]) : 0u;
       const bool isnew = valid && (below ? fpred != f1 : lp != f1);
       const bool islast = valid && (same >> lane) == 1ull;   // highest lane of its group
-      if (isnew) atomicAdd(cnt + cl, 1u);
-      if (islast) last[cl] = f1;
+      if (NARROW) {
+        if (isnew) atomicAdd(cnt2 + (cl >> 1), 1u << ((cl & 1u) * 16));
+        if (islast) last16[cl] = (uint16_t)f1;
+      } else {
+        if (isnew) atomicAdd(cnt + cl, 1u);
+        if (islast) last[cl] = f1;
+      }
+    }
     }
     const uint64_t cend = cid0 + cb < d.nc ? cid0 + cb : d.nc;
     for (uint32_t k = lane; k < cb; k += 64) {
       if (cid0 + k >= cend) break;
-      if (nseg == 1) gcnt[cid0 + k] = cnt[k];
-      else if (cnt[k]) atomicAdd(gcnt + cid0 + k, cnt[k]);
+      const uint32_t ck = NARROW ? (cnt2[k >> 1] >> ((k & 1u) * 16)) & 0xFFFFu : cnt[k];
+      if (nseg == 1) gcnt[cid0 + k] = ck;
+      else if (ck) atomicAdd(gcnt + cid0 + k, ck);
     }
   }
 }
 
-static uint32_t count_waves(uint32_t low2) {
-  const size_t per_wave = (size_t)8 << low2;
+static uint32_t count_waves(uint32_t low2, bool narrow) {
+  const size_t per_wave = (size_t)(narrow ? 4 : 8) << low2;
   size_t w = CNT_LDS / per_wave;
-  if (w > 4) w = 4;
+  if (w > 8) w = 8;
   return w ? (uint32_t)w : 1u;
 }
-size_t count_lds_bytes(uint32_t low2) { return (size_t)count_waves(low2) * ((size_t)8 << low2); }
+static size_t count_lds(uint32_t low2, bool narrow) {
+  return (size_t)count_waves(low2, narrow) * ((size_t)(narrow ? 4 : 8) << low2);
+}
+size_t count_lds_bytes(uint32_t low2) { return count_lds(low2, false); }
 
 // ------------------------------------------------------------------ host side
 DedupShape dedup_shape(uint64_t nc, uint64_t m) {
@@ -580,21 +617,27 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   e = xscan(d.nseg, nf, d.scan_tmp, d.seg0, s);
   if (e != hipSuccess) return e;
-  const uint32_t wv = count_waves(d.low2);
+  const bool nar = d.narrow != 0;
+  const uint32_t wv = count_waves(d.low2, nar);
   const uint32_t gc = (uint32_t)n_cu * 2;
-  const size_t lds = count_lds_bytes(d.low2);
-  if (d.w2 == 4) hipLaunchKernelGGL(k_count<uint32_t>, dim3(gc), dim3(64 * wv), lds, s, d);
-  else hipLaunchKernelGGL(k_count<uint64_t>, dim3(gc), dim3(64 * wv), lds, s, d);
+  const size_t lds = count_lds(d.low2, nar);
+  if (d.w2 == 4) {
+    if (nar) hipLaunchKernelGGL((k_count<uint32_t, 1>), dim3(gc), dim3(64 * wv), lds, s, d);
+    else hipLaunchKernelGGL((k_count<uint32_t, 0>), dim3(gc), dim3(64 * wv), lds, s, d);
+  } else {
+    if (nar) hipLaunchKernelGGL((k_count<uint64_t, 1>), dim3(gc), dim3(64 * wv), lds, s, d);
+    else hipLaunchKernelGGL((k_count<uint64_t, 0>), dim3(gc), dim3(64 * wv), lds, s, d);
+  }
   return hipGetLastError();
 }
 
 hipError_t prepare_dedup(uint32_t low2) {
-  const int lds = (int)count_lds_bytes(low2);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count<uint32_t>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count<uint64_t>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lds);
+  const int l0 = (int)count_lds(low2, false), l1 = (int)count_lds(low2, true);
+  const void *fns[4] = {reinterpret_cast<const void *>(k_count<uint32_t, 0>), reinterpret_cast<const void *>(k_count<uint64_t, 0>),
+                        reinterpret_cast<const void *>(k_count<uint32_t, 1>), reinterpret_cast<const void *>(k_count<uint64_t, 1>)};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; i++)
+    e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 2 ? l0 : l1);
   return e;
 }
 

@@ -181,6 +181,7 @@ struct DedupParams {
   uint64_t *seg0;                // nb1*nb2 + 1: scan of nseg
   void *cnt;                     // u32 counts, nc entries
   uint64_t nc;
+  uint32_t narrow;               // fewer than 65535 sequences: 16-bit per-candidate state in k_count
   uint32_t *status;
 };
 DedupShape dedup_shape(uint64_t nc, uint64_t m);

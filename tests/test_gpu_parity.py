@@ -173,6 +173,19 @@ def test_featurize_loaded_corpus(workload, m, ns, k):
         g.close()
 
 
+def test_many_short_sequences():
+    """More than 65535 sequences: the counting kernels' 32-bit per-candidate state (the narrow
+    16-bit form covers every smaller corpus)."""
+    rng = np.random.default_rng(31)
+    files = [rng.integers(0, 6, size=int(rng.integers(0, 14)), dtype=np.uint8).tobytes() for _ in range(70000)]
+    corpus = gen.from_files(files)
+    say("70000 short sequences, n=1..5")
+    exp, _ = oracle_tables(corpus, [1, 2, 3, 4, 5], 3000)
+    got, g = gpu_tables(corpus, [1, 2, 3, 4, 5], 3000)
+    g.close()
+    assert_tables_equal(got, exp, "70000 sequences")
+
+
 def test_edge_cases():
     cases = [
         ("empty corpus", [], [1, 2], 10),
