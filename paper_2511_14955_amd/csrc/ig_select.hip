@@ -106,18 +106,54 @@ __global__ void k_cnt_pick(SelState *st, unsigned long long *hist, uint32_t shif
   hist[threadIdx.x] = 0;
 }
 
-__global__ void k_collect(SelectParams sp, SelState *st, uint32_t *sel_cid, unsigned long long *sel_cnt,
-                          uint32_t *tie) {
+// Candidates above the threshold T go to sel_*, those equal to T to tie.  Each workgroup takes a
+// contiguous range: it counts its hits per thread, scans the counts in LDS, reserves its output
+// with one device atomic per list, then re-reads the range and writes at the scanned positions.
+// (Output order is irrelevant: the selection is sorted by count and key afterwards.)
+__global__ void __launch_bounds__(256) k_collect(SelectParams sp, SelState *st, uint32_t *sel_cid,
+                                                 unsigned long long *sel_cnt, uint32_t *tie) {
+  __shared__ uint32_t s_gt[256], s_eq[256];
+  __shared__ unsigned long long s_base[2];
   if (!st->kprime) return;
+  const uint32_t tid = threadIdx.x, bs = blockDim.x;
   const uint64_t T = st->T;
-  const uint64_t nc_round = (sp.nc + 63) & ~63ull;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nc_round; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint64_t c = i < sp.nc ? load_cnt(sp.cnt, sp.count64, i) : 0;
-    const bool gt = c > T, eq = c != 0 && c == T;
-    const unsigned long long a = wave_append(&st->nsel, gt);
-    if (gt) { sel_cid[a] = (uint32_t)i; sel_cnt[a] = c; }
-    const unsigned long long b = wave_append(&st->ntie, eq);
-    if (eq) tie[b] = (uint32_t)i;
+  const uint64_t per = ((sp.nc + gridDim.x - 1) / gridDim.x + bs - 1) / bs * bs;
+  const uint64_t lo = (uint64_t)blockIdx.x * per, hi = lo + per < sp.nc ? lo + per : sp.nc;
+  uint32_t ngt = 0, neq = 0;
+  for (uint64_t i = lo + tid; i < hi; i += bs) {
+    const uint64_t c = load_cnt(sp.cnt, sp.count64, i);
+    ngt += c > T ? 1u : 0u;
+    neq += (c != 0 && c == T) ? 1u : 0u;
+  }
+  s_gt[tid] = ngt;
+  s_eq[tid] = neq;
+  __syncthreads();
+  // inclusive scan over the threads (Hillis-Steele in LDS)
+  for (uint32_t off = 1; off < bs; off <<= 1) {
+    const uint32_t a = tid >= off ? s_gt[tid - off] : 0u, e = tid >= off ? s_eq[tid - off] : 0u;
+    __syncthreads();
+    s_gt[tid] += a;
+    s_eq[tid] += e;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    s_base[0] = s_gt[bs - 1] ? atomicAdd(&st->nsel, (unsigned long long)s_gt[bs - 1]) : 0ull;
+    s_base[1] = s_eq[bs - 1] ? atomicAdd(&st->ntie, (unsigned long long)s_eq[bs - 1]) : 0ull;
+  }
+  __syncthreads();
+  if (s_gt[bs - 1] == 0 && s_eq[bs - 1] == 0) return;
+  unsigned long long pg = s_base[0] + s_gt[tid] - ngt, pe = s_base[1] + s_eq[tid] - neq;
+  for (uint64_t i = lo + tid; i < hi && (ngt | neq); i += bs) {
+    const uint64_t c = load_cnt(sp.cnt, sp.count64, i);
+    if (c > T) {
+      sel_cid[pg] = (uint32_t)i;
+      sel_cnt[pg] = c;
+      pg++;
+      ngt--;
+    } else if (c != 0 && c == T) {
+      tie[pe++] = (uint32_t)i;
+      neq--;
+    }
   }
 }
 
