@@ -350,12 +350,16 @@ __global__ void k_fin(DedupParams d) {
 // replays its rounds in order, advancing its own cursors: positions follow the tile order.
 static constexpr uint32_t SLICE_ROUNDS = TILE / P2_BLOCK;   // rounds of 64 per wavefront and tile
 template <typename R1, typename R2>
-__global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
+__global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) k_p2_scatter(DedupParams d) {
   constexpr uint32_t NW = P2_BLOCK / 64;
   __shared__ uint64_t s_base1[257];
   __shared__ uint64_t s_bend[256];
-  __shared__ uint64_t dbase[1024];      // the tile's first position of each digit
-  __shared__ uint32_t wcur[NW][1024];   // per-wavefront cursor of each digit, relative to dbase
+  // sized by the digit count (nb2 <= 1024): the tile's first position of each digit, and each
+  // wavefront's cursor per digit relative to it
+  extern __shared__ __align__(16) uint8_t p2lds[];
+  uint64_t *dbase = reinterpret_cast<uint64_t *>(p2lds);
+  uint32_t *wcur_ = reinterpret_cast<uint32_t *>(p2lds + (size_t)d.nb2 * 8);
+  auto wcur = [&](uint32_t ww, uint32_t k) -> uint32_t & { return wcur_[ww * d.nb2 + k]; };
   if (rec_overflow(d)) return;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (uint32_t i = tid; i <= d.nb1; i += P2_BLOCK) s_base1[i] = d.base1[i];
@@ -367,31 +371,26 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
   const uint32_t m2 = d.low2 >= 32 ? 0xFFFFFFFFu : ((1u << d.low2) - 1);
   const uint64_t lt = (1ull << lane) - 1;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcur[k / d.nb2][k % d.nb2] = 0;
+    for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcur_[k] = 0;
     __syncthreads();
     const uint64_t pos = t * TILE;
     const uint32_t b = tile_bucket(s_base1, d.nb1, pos);
     const uint64_t tb = s_base1[b] / TILE, ntb = (s_base1[b + 1] - s_base1[b]) / TILE, tl = t - tb;
     const uint64_t hi = pos + TILE < s_bend[b] ? pos + TILE : s_bend[b];
     const uint64_t s0 = pos + (uint64_t)w * SLICE_ROUNDS * 64;
-    uint32_t rf[SLICE_ROUNDS], rc[SLICE_ROUNDS], rd[SLICE_ROUNDS];
+    // per round only the record and its digit-match mask stay in registers (sequence, candidate
+    // and digit are decoded again in the replay), which keeps the kernel under 64 VGPRs
+    R1 rr[SLICE_ROUNDS];
     uint64_t rs[SLICE_ROUNDS];
     // pass 1: this wavefront's digit counts
 #pragma unroll
     for (uint32_t q = 0; q < SLICE_ROUNDS; q++) {
       const uint64_t i = s0 + q * 64 + lane;
       const bool valid = i < hi;
-      rf[q] = 0;
-      rc[q] = 0;
-      rd[q] = 0;
-      if (valid) {
-        const R1 r = in[i];
-        rf[q] = Rec<R1>::file(r, d.low1);
-        rc[q] = Rec<R1>::cl(r, d.low1);
-        rd[q] = (rc[q] >> d.low2) & dm;
-      }
-      rs[q] = wave_match(rd[q], d.b2bits, valid);
-      if (valid && (rs[q] & lt) == 0) wcur[w][rd[q]] += (uint32_t)__popcll(rs[q]);
+      rr[q] = valid ? in[i] : (R1)0;
+      const uint32_t rd = (Rec<R1>::cl(rr[q], d.low1) >> d.low2) & dm;
+      rs[q] = wave_match(rd, d.b2bits, valid);
+      if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
     }
     __syncthreads();
     // per digit: the tile's first position, then each wavefront's offset from it
@@ -399,8 +398,8 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
       dbase[k] = d.g2[tb * d.nb2 + (uint64_t)k * ntb + tl];
       uint32_t off = 0;
       for (uint32_t ww = 0; ww < NW; ww++) {
-        const uint32_t x = wcur[ww][k];
-        wcur[ww][k] = off;
+        const uint32_t x = wcur(ww, k);
+        wcur(ww, k) = off;
         off += x;
       }
     }
@@ -410,13 +409,14 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_scatter(DedupParams d) {
     for (uint32_t q = 0; q < SLICE_ROUNDS; q++) {
       const uint64_t i = s0 + q * 64 + lane;
       const bool valid = i < hi;
+      const uint32_t rc = Rec<R1>::cl(rr[q], d.low1), rd = (rc >> d.low2) & dm;
       if (valid) {
-        const uint64_t at = dbase[rd[q]] + wcur[w][rd[q]] + (uint32_t)__popcll(rs[q] & lt);
-        if (at < d.cap) out[at] = Rec<R2>::pack(rf[q], rc[q] & m2, d.low2);
+        const uint64_t at = dbase[rd] + wcur(w, rd) + (uint32_t)__popcll(rs[q] & lt);
+        if (at < d.cap) out[at] = Rec<R2>::pack(Rec<R1>::file(rr[q], d.low1), rc & m2, d.low2);
       }
       // every lane has read its cursor before the group's first lane advances it
       __builtin_amdgcn_wave_barrier();
-      if (valid && (rs[q] & lt) == 0) wcur[w][rd[q]] += (uint32_t)__popcll(rs[q]);
+      if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
@@ -606,10 +606,11 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin, dim3((d.nb1 * d.nb2 + 256) / 256), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (d.w1 == 4 && d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
-  else if (d.w1 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
-  else if (d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
-  else hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), 0, s, d);
+  const size_t p2l = (size_t)d.nb2 * 8 + (size_t)(P2_BLOCK / 64) * d.nb2 * 4;
+  if (d.w1 == 4 && d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
+  else if (d.w1 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
+  else if (d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
+  else hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // segments of at most SEG records, cut at sequence boundaries, so that a hot bucket is shared out
   const uint32_t nf = d.nb1 * d.nb2;
