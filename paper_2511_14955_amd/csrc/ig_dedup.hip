@@ -89,52 +89,13 @@ __global__ void __launch_bounds__(256) k_xscan_reduce(const uint32_t *in, uint64
 // exclusive scan of np partials in place (one workgroup), total to *total; with ndev, np and
 // the total's position follow the device count (out + n)
 __global__ void __launch_bounds__(1024) k_xscan_top(uint64_t *part, uint64_t np, uint64_t *total) {
-  __shared__ uint64_t s[1024];
-  const uint32_t t = threadIdx.x;
-  const uint64_t per = (np + 1023) / 1024, lo = t * per, hi = lo + per < np ? lo + per : np;
-  uint64_t acc = 0;
-  for (uint64_t i = lo; i < hi; i++) acc += part[i];
-  s[t] = acc;
-  __syncthreads();
-  for (uint32_t o = 1; o < 1024; o <<= 1) {
-    const uint64_t x = t >= o ? s[t - o] : 0;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }
-  uint64_t run = s[t] - acc;
-  for (uint64_t i = lo; i < hi; i++) {
-    const uint64_t v = part[i];
-    part[i] = run;
-    run += v;
-  }
-  if (t == 1023) *total = s[1023];
+  wg_exclusive_scan<uint64_t>(part, np, total);
 }
 
 __global__ void __launch_bounds__(1024) k_xscan_top_d(uint64_t *part, uint64_t n0, const uint64_t *ndev, uint32_t mult,
                                                       uint64_t *out) {
-  __shared__ uint64_t s[1024];
   const uint64_t n = scan_len(n0, ndev, mult);
-  const uint64_t np = (n + SCAN_SEG - 1) / SCAN_SEG;
-  const uint32_t t = threadIdx.x;
-  const uint64_t per = (np + 1023) / 1024, lo = t * per, hi = lo + per < np ? lo + per : np;
-  uint64_t acc = 0;
-  for (uint64_t i = lo; i < hi; i++) acc += part[i];
-  s[t] = acc;
-  __syncthreads();
-  for (uint32_t o = 1; o < 1024; o <<= 1) {
-    const uint64_t x = t >= o ? s[t - o] : 0;
-    __syncthreads();
-    s[t] += x;
-    __syncthreads();
-  }
-  uint64_t run = s[t] - acc;
-  for (uint64_t i = lo; i < hi; i++) {
-    const uint64_t v = part[i];
-    part[i] = run;
-    run += v;
-  }
-  if (t == 1023) out[n] = s[1023];
+  wg_exclusive_scan<uint64_t>(part, (n + SCAN_SEG - 1) / SCAN_SEG, out + n);
 }
 
 __global__ void __launch_bounds__(256) k_xscan_apply(const uint32_t *in, uint64_t n0, const uint64_t *ndev, uint32_t mult,

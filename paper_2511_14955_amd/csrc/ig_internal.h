@@ -88,6 +88,61 @@ __device__ __forceinline__ uint32_t map_fp(uint64_t h, uint32_t rank_bits) {
   return rank_bits >= 32 ? 0u : (uint32_t)(h >> (32 + rank_bits));
 }
 
+// Exclusive scan of a[0, len) in place by one workgroup of 1024 threads (16 wavefronts): blocks
+// of 4096 elements, 4 consecutive per thread (coalesced), wavefront scans by shuffles, the
+// wavefront sums scanned in LDS, and a carry between blocks.  *total_out (if given) = the sum.
+template <typename T> __device__ __forceinline__ T shfl_up_t(T x, uint32_t d) {
+  if constexpr (sizeof(T) == 8) {
+    const uint32_t lo = __shfl_up((unsigned)(x & 0xFFFFFFFFull), d), hi = __shfl_up((unsigned)(x >> 32), d);
+    return ((T)hi << 32) | (T)lo;
+  } else {
+    return (T)__shfl_up((unsigned)x, d);
+  }
+}
+template <typename T> __device__ void wg_exclusive_scan(T *a, uint64_t len, T *total_out) {
+  __shared__ T wsum[16];
+  __shared__ T carry;
+  const uint32_t t = threadIdx.x, lane = t & 63, w = t >> 6;
+  if (t == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t base = 0; base < len; base += 4096) {
+    T v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint64_t i = base + (uint64_t)t * 4 + q;
+      v[q] = i < len ? a[i] : (T)0;
+      sum += v[q];
+    }
+    T x = sum;
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+      const T y = shfl_up_t(x, off);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (t < 64) {
+      T ws = lane < 16 ? wsum[lane] : (T)0;
+      for (uint32_t off = 1; off < 16; off <<= 1) {
+        const T y = shfl_up_t(ws, off);
+        if (lane >= off) ws += y;
+      }
+      if (lane < 16) wsum[lane] = ws;   // inclusive over the wavefronts
+    }
+    __syncthreads();
+    T run = carry + (w ? wsum[w - 1] : (T)0) + x - sum;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const uint64_t i = base + (uint64_t)t * 4 + q;
+      if (i < len) a[i] = run;
+      run += v[q];
+    }
+    __syncthreads();   // carry and wsum have been read
+    if (t == 0) carry += wsum[15];
+    __syncthreads();
+  }
+  if (t == 0 && total_out) *total_out = carry;
+}
+
 // ------------------------------------------------------------------ shared structs
 struct Chunk {
   uint64_t s0;      // first symbol (absolute) whose window this chunk owns

@@ -290,26 +290,7 @@ __global__ void __launch_bounds__(64) k_sort_hist(const SelState *st, const uint
 
 // exclusive scan of hist[256 * ntiles] (digit-major) in one workgroup
 __global__ void __launch_bounds__(1024) k_sort_scan(uint32_t *hist, uint64_t len) {
-  __shared__ uint32_t part[1024];
-  const uint32_t t = threadIdx.x;
-  const uint64_t per = (len + 1023) / 1024;
-  const uint64_t lo = t * per, hi = lo + per < len ? lo + per : len;
-  uint32_t s = 0;
-  for (uint64_t i = lo; i < hi; i++) s += hist[i];
-  part[t] = s;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    uint32_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[t] - s;
-  for (uint64_t i = lo; i < hi; i++) {
-    const uint32_t v = hist[i];
-    hist[i] = run;
-    run += v;
-  }
+  wg_exclusive_scan<uint32_t>(hist, len, nullptr);
 }
 
 __global__ void __launch_bounds__(64) k_sort_scatter(const SelState *st, const uint64_t *klo, const uint64_t *khi,
