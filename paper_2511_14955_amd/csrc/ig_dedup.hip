@@ -206,39 +206,73 @@ __global__ void __launch_bounds__(256) k_bases(DedupParams d) {
 // ------------------------------------------------------------------ level-1 gather
 template <typename R1>
 __global__ void __launch_bounds__(256) k_gather(DedupParams d) {
-  __shared__ uint64_t s_base[256];
-  __shared__ uint32_t s_cur[256];
+  // Records go through LDS in tiles of GT, counting-sorted by bucket, so that consecutive lanes
+  // write consecutive positions of one bucket's run (a direct scatter sends each lane of a store
+  // to a different bucket, so to a different cache line).
+  constexpr uint32_t GT = 2048, PER = GT / 256;
+  __shared__ uint64_t s_base[256];   // the chunk's first position in each bucket
+  __shared__ uint32_t s_cur[256];    // records of the chunk already written per bucket
+  __shared__ uint32_t s_h[256];      // the tile's records per bucket
+  __shared__ uint32_t s_off[256];    // the tile's first sorted slot per bucket
+  __shared__ uint32_t s_wsum[4];
+  __shared__ uint32_t s_stage[GT];
   if (rec_overflow(d)) return;
-  const uint32_t tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t per = (d.nct + gridDim.x - 1) / gridDim.x;
   const uint32_t c0 = blockIdx.x * per, c1 = c0 + per < d.nct ? c0 + per : d.nct;
   R1 *out = reinterpret_cast<R1 *>(d.l1);
   const uint32_t m1 = d.low1 >= 32 ? 0xFFFFFFFFu : ((1u << d.low1) - 1);
+  auto bucket = [&](uint32_t cid) {
+    uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
+    return b < d.nb1 ? b : d.nb1 - 1;   // (only a corrupt record could exceed the candidate space)
+  };
   for (uint32_t ci = c0; ci < c1; ci++) {
     const Chunk c = d.chunks[ci];
     const uint32_t n = d.nrec[ci] < c.nsym ? d.nrec[ci] : c.nsym;   // a chunk records at most one per window
     if (n == 0) continue;   // uniform across the workgroup
-    for (uint32_t b = tid; b < d.nb1; b += 256) {
-      s_base[b] = d.g1[(uint64_t)ci * d.nb1 + b] + d.bshift[b];
-      s_cur[b] = 0;
+    if (tid < d.nb1) {
+      s_base[tid] = d.g1[(uint64_t)ci * d.nb1 + tid] + d.bshift[tid];
+      s_cur[tid] = 0;
     }
-    __syncthreads();
     const uint32_t *src = d.rec0 + c.s0;
-    // four records per thread: their loads are issued before the first cursor atomic
-    for (uint32_t i0 = tid; i0 < n; i0 += 4 * 256) {
-      uint32_t cids[4];
+    for (uint32_t t0 = 0; t0 < n; t0 += GT) {
+      const uint32_t m = n - t0 < GT ? n - t0 : GT;
+      s_h[tid] = 0;
+      __syncthreads();
+      // this thread's records of the tile (loads first), their buckets and ranks within them
+      uint32_t cid[PER], rk[PER];
 #pragma unroll
-      for (uint32_t q = 0; q < 4; q++) cids[q] = src[i0 + q * 256 < n ? i0 + q * 256 : n - 1];   // n >= 1
+      for (uint32_t q = 0; q < PER; q++) cid[q] = src[t0 + (q * 256 + tid < m ? q * 256 + tid : m - 1)];
 #pragma unroll
-      for (uint32_t q = 0; q < 4; q++) {
-        if (i0 + q * 256 >= n) break;
-        const uint32_t cid = cids[q];
-        uint32_t b = d.low1 >= 32 ? 0u : (cid >> d.low1);
-        if (b >= d.nb1) b = d.nb1 - 1;   // (only a corrupt record could exceed the candidate space)
-        const uint32_t k = atomicAdd(s_cur + b, 1u);
-        const uint64_t at = s_base[b] + k;
-        if (at < d.cap) out[at] = Rec<R1>::pack(c.file, cid & m1, d.low1);
+      for (uint32_t q = 0; q < PER; q++)
+        rk[q] = q * 256 + tid < m ? atomicAdd(s_h + bucket(cid[q]), 1u) : 0u;
+      __syncthreads();
+      // exclusive scan of the tile's bucket counts (one bucket per thread)
+      const uint32_t hv = s_h[tid];
+      uint32_t x = hv;
+      for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
       }
+      if (lane == 63) s_wsum[w] = x;
+      __syncthreads();
+      uint32_t wb = 0;
+      for (uint32_t ww = 0; ww < w; ww++) wb += s_wsum[ww];
+      s_off[tid] = wb + x - hv;
+      __syncthreads();
+#pragma unroll
+      for (uint32_t q = 0; q < PER; q++)
+        if (q * 256 + tid < m) s_stage[s_off[bucket(cid[q])] + rk[q]] = cid[q];
+      __syncthreads();
+      // sorted slots: slot j of bucket b goes to the chunk's run in b
+      for (uint32_t j = tid; j < m; j += 256) {
+        const uint32_t v = s_stage[j];
+        const uint32_t b = bucket(v);
+        const uint64_t at = s_base[b] + s_cur[b] + (j - s_off[b]);
+        if (at < d.cap) out[at] = Rec<R1>::pack(c.file, v & m1, d.low1);
+      }
+      __syncthreads();
+      if (tid < d.nb1) s_cur[tid] += s_h[tid];
     }
     __syncthreads();
   }
