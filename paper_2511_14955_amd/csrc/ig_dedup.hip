@@ -355,6 +355,11 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
   uint64_t *dbase = reinterpret_cast<uint64_t *>(p2lds);
   uint32_t *wcur_ = reinterpret_cast<uint32_t *>(p2lds + (size_t)d.nb2 * 8);
   auto wcur = [&](uint32_t ww, uint32_t k) -> uint32_t & { return wcur_[ww * d.nb2 + k]; };
+  // the tile sorted by digit in LDS (stable), written out in order: consecutive lanes then store
+  // consecutive positions of one digit's run
+  uint32_t *toff = wcur_ + (size_t)NW * d.nb2;                            // the tile's first slot per digit
+  R2 *stage = reinterpret_cast<R2 *>(toff + d.nb2 + (d.nb2 & 1));         // TILE records (8-byte aligned)
+  uint16_t *sdig = reinterpret_cast<uint16_t *>(stage + TILE);            // their digits
   if (rec_overflow(d)) return;
   const uint32_t tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (uint32_t i = tid; i <= d.nb1; i += P2_BLOCK) s_base1[i] = d.base1[i];
@@ -388,7 +393,7 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
       if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
     }
     __syncthreads();
-    // per digit: the tile's first position, then each wavefront's offset from it
+    // per digit: the tile's first position, each wavefront's offset from it, the digit's total
     for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) {
       dbase[k] = d.g2[tb * d.nb2 + (uint64_t)k * ntb + tl];
       uint32_t off = 0;
@@ -396,6 +401,25 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
         const uint32_t x = wcur(ww, k);
         wcur(ww, k) = off;
         off += x;
+      }
+      toff[k] = off;
+    }
+    __syncthreads();
+    // exclusive scan of the digit totals (one wavefront, nb2 / 64 consecutive digits per lane)
+    if (w == 0) {
+      const uint32_t per = (d.nb2 + 63) / 64, k0 = lane * per, k1 = k0 + per < d.nb2 ? k0 + per : d.nb2;
+      uint32_t sum = 0;
+      for (uint32_t k = k0; k < k1; k++) sum += toff[k];
+      uint32_t x = sum;
+      for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+      }
+      uint32_t run = x - sum;
+      for (uint32_t k = k0; k < k1; k++) {
+        const uint32_t v = toff[k];
+        toff[k] = run;
+        run += v;
       }
     }
     __syncthreads();
@@ -406,13 +430,21 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
       const bool valid = i < hi;
       const uint32_t rc = Rec<R1>::cl(rr[q], d.low1), rd = (rc >> d.low2) & dm;
       if (valid) {
-        const uint64_t at = dbase[rd] + wcur(w, rd) + (uint32_t)__popcll(rs[q] & lt);
-        if (at < d.cap) out[at] = Rec<R2>::pack(Rec<R1>::file(rr[q], d.low1), rc & m2, d.low2);
+        const uint32_t slot = toff[rd] + wcur(w, rd) + (uint32_t)__popcll(rs[q] & lt);
+        stage[slot] = Rec<R2>::pack(Rec<R1>::file(rr[q], d.low1), rc & m2, d.low2);
+        sdig[slot] = (uint16_t)rd;
       }
       // every lane has read its cursor before the group's first lane advances it
       __builtin_amdgcn_wave_barrier();
       if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
       __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const uint32_t tlen = (uint32_t)(hi > pos ? hi - pos : 0);
+    for (uint32_t j = tid; j < tlen; j += P2_BLOCK) {
+      const uint32_t dg = sdig[j];
+      const uint64_t at = dbase[dg] + (j - toff[dg]);
+      if (at < d.cap) out[at] = stage[j];
     }
     __syncthreads();
   }
@@ -601,7 +633,8 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_fin, dim3((d.nb1 * d.nb2 + 256) / 256), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t p2l = (size_t)d.nb2 * 8 + (size_t)(P2_BLOCK / 64) * d.nb2 * 4;
+  const size_t p2l = (size_t)d.nb2 * 8 + (size_t)(P2_BLOCK / 64) * d.nb2 * 4 + (size_t)(d.nb2 + (d.nb2 & 1)) * 4 +
+                     (size_t)TILE * d.w2 + (size_t)TILE * 2;
   if (d.w1 == 4 && d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
   else if (d.w1 == 4) hipLaunchKernelGGL((k_p2_scatter<uint32_t, uint64_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
   else if (d.w2 == 4) hipLaunchKernelGGL((k_p2_scatter<uint64_t, uint32_t>), dim3(g2), dim3(P2_BLOCK), p2l, s, d);
@@ -634,6 +667,13 @@ hipError_t prepare_dedup(uint32_t low2) {
   hipError_t e = hipSuccess;
   for (int i = 0; i < 4 && e == hipSuccess; i++)
     e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, i < 2 ? l0 : l1);
+  // the level-2 scatter stages a tile: up to 1024 digits and 8-byte records need about 84 KB
+  const void *p2[4] = {reinterpret_cast<const void *>(k_p2_scatter<uint32_t, uint32_t>),
+                       reinterpret_cast<const void *>(k_p2_scatter<uint32_t, uint64_t>),
+                       reinterpret_cast<const void *>(k_p2_scatter<uint64_t, uint32_t>),
+                       reinterpret_cast<const void *>(k_p2_scatter<uint64_t, uint64_t>)};
+  for (int i = 0; i < 4 && e == hipSuccess; i++)
+    e = hipFuncSetAttribute(p2[i], hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
   return e;
 }
 
