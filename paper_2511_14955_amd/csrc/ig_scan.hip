@@ -10,7 +10,10 @@
 // loads, then each thread rolls a key across a contiguous run of windows.
 // The prefix test first consults a compact filter image held in LDS (a direct
 // bitmap when the prefix space is small, otherwise a blocked Bloom filter with
-// no false negatives); only filter hits probe the exact key -> rank map.
+// no false negatives); only filter hits probe the exact key -> rank map.  For keys
+// of at most 64 bits the hits are first compacted into a per-wavefront LDS ring and
+// resolved 64 at a time, one lane each (one 8-byte quotient-map read when the table
+// has one); the others are resolved in place.
 // Survivors become dense candidate ids, de-duplicated per chunk in an LDS hash
 // set.  For Eq. 1 the set also holds per-candidate counts that are added to the
 // count array at the end of the chunk.  For Eq. 2 the chunk writes its distinct

@@ -1,9 +1,10 @@
 // Index over the retained table, and featurization against it.
 //
-// After a pass (Algorithm 3's "P^(j) <- zk-argmax") the retained keys are
-// indexed twice:
+// After a pass (Algorithm 3's selection of P^(j)) the retained keys are indexed:
 //  * an exact open-addressing map key -> rank+1 (capacity a power of two, at
 //    least twice the table), probed only by filter hits;
+//  * for keys of at most 64 bits, a quotient map of the same capacity whose 8-byte
+//    slots identify their key without a second read (see QMapShape);
 //  * a compact filter image that a scan workgroup copies into LDS: a direct
 //    bitmap over the whole key space when it is small enough (exact), else a
 //    blocked Bloom filter (three bits in one 32-bit word chosen by the key hash;
