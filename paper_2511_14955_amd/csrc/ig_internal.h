@@ -54,13 +54,26 @@ struct QMapShape {
   uint32_t w, sbits, qbits, rbits, dbits;
 };
 __host__ __device__ __forceinline__ uint64_t qmix(uint64_t x, uint32_t w) {
+  // one round: the multiply carries every bit into the top bits (the home slot), the last
+  // xor-shift folds the top bits into the stored low bits
   const uint64_t m = w >= 64 ? ~0ull : ((1ull << w) - 1);
   const uint32_t s = (w + 1) >> 1;
   x ^= x >> s;
   x = (x * 0xFF51AFD7ED558CCDull) & m;
-  x ^= x >> s;
-  x = (x * 0xC4CEB9FE1A85EC53ull) & m;
   return x ^ (x >> s);
+}
+// Blocked Bloom filter position of a key (filter of `words` 32-bit words, a power of two): an
+// xor-shift, a fold to 32 bits and one 32 x 32 -> 64-bit multiply; the word and the three bits
+// come from the product's high word.  (The fold only adds collisions of about k / 2^32 per
+// query; a filter has no false negatives either way.)
+__host__ __device__ __forceinline__ uint32_t bloom_fold(uint64_t lo, uint64_t hi) {
+  const uint64_t x = lo ^ (lo >> 29) ^ hi ^ (hi >> 23);
+  return (uint32_t)x ^ (uint32_t)(x >> 32);
+}
+__host__ __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t words, uint32_t *word, uint32_t *mask) {
+  const uint32_t t = (uint32_t)(((uint64_t)v * 0x9E3779B1ull) >> 32);
+  *word = t & (words - 1);
+  *mask = (1u << ((t >> 14) & 31)) | (1u << ((t >> 19) & 31)) | (1u << ((t >> 24) & 31));
 }
 __host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
   x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;

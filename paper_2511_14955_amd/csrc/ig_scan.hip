@@ -80,8 +80,11 @@ __device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t l
 }
 
 // LDS open-addressing set of candidate ids: 1 = newly inserted, 0 = present, -1 = full.
-__device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t cid, uint32_t *slot_out) {
-  uint32_t h = hash32(cid) & capmask;
+// The home slot is the top bits of cid times an odd constant (one multiply; the candidate ids of a
+// chunk are dense ranks times sigma plus a code, which the product spreads over the top bits).
+__device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t capshift, uint32_t cid,
+                                          uint32_t *slot_out) {
+  uint32_t h = (cid * 0x9E3779B1u) >> capshift;
   for (int i = 0; i < 64; i++) {
     const uint32_t cur = atomicCAS(s_set + h, LDS_EMPTY, cid);
     if (cur == LDS_EMPTY) { *slot_out = h; return 1; }
@@ -121,6 +124,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   const uint64_t mlo = (KW == 1) ? (nb >= 64 ? ~0ull : ((1ull << nb) - 1)) : ~0ull;
   const uint64_t mhi = (KW == 2) ? (nb >= 128 ? ~0ull : ((1ull << (nb - 64)) - 1)) : 0ull;
   const uint32_t capmask = p.set_cap - 1;
+  const uint32_t capshift = 32u - (uint32_t)__builtin_ctz(p.set_cap);   // set_cap is a power of two
   const uint32_t fmask = p.filt_words - 1;
 
   if (MODE == MODE_FILTERED)
@@ -196,7 +200,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     // one surviving candidate: de-duplicate in the chunk's LDS set
     auto handle = [&](uint32_t cid) {
       uint32_t slot;
-      const int ins = lds_insert(s_set, capmask, cid, &slot);
+      const int ins = lds_insert(s_set, capmask, capshift, cid, &slot);
       if (OCC) {
         if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
         else cnt_add<CT>(p.cnt, cid, (CT)1);
@@ -287,9 +291,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           kk[u] = k.lo;
           const uint64_t plo = k.lo >> B;
           if (bloom) {
-            const uint64_t h = hash_key(plo, 0);
-            widx[u] = (uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32);
-            bm[u] = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+            bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
           } else {
             widx[u] = direct ? (uint32_t)(plo >> 5) & fmask : 0u;
             bm[u] = direct ? 1u << (plo & 31) : 0u;
@@ -341,15 +343,13 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
             uint64_t h = 0;
             if (p.filt_kind == FILT_DIRECT) {
               if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
-              h = hash_key(plo, phi);
-            } else {
-              h = hash_key(plo, phi);
-              if (p.filt_kind == FILT_BLOOM) {
-                const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
-                const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
-                if ((w & bm) != bm) continue;
-              }
+            } else if (p.filt_kind == FILT_BLOOM) {
+              uint32_t wi, bm;
+              bloom_pos(bloom_fold(plo, phi), p.filt_words, &wi, &bm);
+              const uint32_t w = s_filt[wi];
+              if ((w & bm) != bm) continue;
             }
+            h = hash_key(plo, phi);
             const uint64_t slot = h & p.mmask;
             q_slot[u] = slot;
             q_v[u] = p.map[slot];

@@ -67,9 +67,9 @@ __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const u
     if (kind == FILT_DIRECT) {
       atomicOr(filt + (lo >> 5), 1u << (lo & 31));
     } else {
-      const uint64_t h = hash_key(lo, hi);
-      const uint32_t w = (uint32_t)(((h >> 32) * (uint64_t)words) >> 32);
-      atomicOr(filt + w, (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31)));
+      uint32_t w, bm;
+      bloom_pos(bloom_fold(lo, hi), words, &w, &bm);
+      atomicOr(filt + w, bm);
     }
   }
 }
@@ -87,9 +87,8 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     words = (uint32_t)(((1ull << nbits) + 31) / 32);
   } else {
     kind = FILT_BLOOM;
-    uint64_t w = (k_max * 12 + 31) / 32;
-    if (w < 64) w = 64;
-    if (w > maxw) w = maxw;
+    uint64_t w = 64;   // about 12 bits per key, a power of two within [64, maxw]
+    while (w < (k_max * 12 + 31) / 32 && w < maxw) w <<= 1;
     words = (uint32_t)w;
   }
   uint32_t rb = 1;
@@ -216,14 +215,15 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
         for (uint32_t r = 0; r + 1 < n; r++) push(sym(wbeg + t_lo + r));
         for (uint64_t t = t_lo; t < t_hi; t++) {
           push(sym(wbeg + t + n - 1));
-          const uint64_t h = hash_key(klo, khi);
           if (p.filt_kind == FILT_DIRECT) {
             if (!((s_filt[klo >> 5] >> (klo & 31)) & 1u)) continue;
           } else {
-            const uint32_t w = s_filt[(uint32_t)(((h >> 32) * (uint64_t)p.filt_words) >> 32)];
-            const uint32_t bm = (1u << (h & 31)) | (1u << ((h >> 5) & 31)) | (1u << ((h >> 10) & 31));
+            uint32_t wi, bm;
+            bloom_pos(bloom_fold(klo, khi), p.filt_words, &wi, &bm);
+            const uint32_t w = s_filt[wi];
             if ((w & bm) != bm) continue;
           }
+          const uint64_t h = hash_key(klo, khi);
           uint64_t slot = h & p.mmask;
           int64_t r = -1;
           const uint32_t fp = map_fp(h, p.rank_bits);
