@@ -75,10 +75,6 @@ __host__ __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t words, u
   *word = t & (words - 1);
   *mask = (1u << ((t >> 14) & 31)) | (1u << ((t >> 19) & 31)) | (1u << ((t >> 24) & 31));
 }
-__host__ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
-  x ^= x >> 16; x *= 0x7feb352dU; x ^= x >> 15; x *= 0x846ca68bU; x ^= x >> 16;
-  return x;
-}
 
 // Lanes of this wavefront whose `key` (its low `nbits` bits) equals this lane's, among the
 // valid lanes (the wavefront's analogue of a match instruction: one ballot per key bit).
