@@ -368,8 +368,9 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   }
   p.set_cap = c->lc.set_cap;
   p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
-  // the LDS check assumes the largest level-1 histogram (256 buckets per wavefront)
-  p.hist_words = occ ? 0u : (c->lc.block / 64) * 256u;
+  // level-1 histogram: a filtered pass knows its bucket count now (its candidate space is fixed);
+  // the other passes assume the largest (256 buckets per wavefront)
+  p.hist_words = occ ? 0u : (c->lc.block / 64) * (mode == MODE_FILTERED ? dedup_shape(nc, c->m).nb1 : 256u);
   p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 8u : 0u;
   // without LDS for the survivor rings the scan resolves survivors in place; so it does when
   // the previous table holds every (n-1)-gram over the alphabet (every window survives)

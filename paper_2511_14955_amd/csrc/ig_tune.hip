@@ -83,14 +83,15 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
     }
     return IG_OK;
   }
-  // Chunk lengths are multiples of 1024 symbols whose per-thread window runs (chunk / 1024,
-  // made odd) split well into the scan's batches of 8; 512-thread blocks are kept as a
-  // fallback for small corpora.  Shapes that do not fit the pass's LDS are skipped.
+  // Chunk lengths are multiples of 1024 symbols (per-thread window runs of chunk / 1024, made
+  // odd); 512-thread blocks are kept as a fallback for small corpora, and the largest LDS set
+  // only with the shorter chunks.  Shapes that do not fit the pass's LDS are skipped.
   std::vector<LaunchCfg> cands;
-  for (uint32_t cs : {15360u, 16384u, 23552u, 31744u, 32768u})
+  for (uint32_t cs : {15360u, 16384u, 19456u, 23552u, 27648u, 31744u})
     for (uint32_t bl : {512u, 1024u})
       for (uint32_t sc : {4096u, 8192u, 16384u}) {
         if (bl == 512 && cs > 16384) continue;
+        if (sc == 16384 && cs > 16384) continue;
         LaunchCfg lc = start;
         lc.chunk_syms = cs;
         lc.block = bl;
