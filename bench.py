@@ -86,6 +86,36 @@ def recall_sample(ig, n, k_keep, corpus, zs=(1.0, 1.5, 2.0)):
             "algorithm3": sched}
 
 
+def hbm_read_attainable(nbytes=4 << 30, reps=5):
+    """Read bandwidth a plain streaming reduction attains on this GPU (context for the roofline):
+    torch.sum over nbytes of float32, timed with events after one warm-up."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    x.sum()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x
+    torch.cuda.empty_cache()
+    return {"GB_per_s": round(nbytes / (ms * 1e-3) / 1e9, 1), "bytes": nbytes, "kernel": "torch.sum float32"}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, k_keep, sample_files, threads):
     """The CPU oracle as it stands, on the first sample_files files of the same corpus."""
     import gen
@@ -98,9 +128,20 @@ def cpu_baseline(n, k_keep, sample_files, threads):
     t0 = time.perf_counter()
     assert o.pass_(n, k_keep) == 0
     dt = time.perf_counter() - t0
+    # one thread on the tiny plain run (64 files x 64 KiB, n = 1..4, k = 1000)
+    tiny = gen.workload(1)
+    o1 = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=1)
+    o1.load(tiny)
+    t1 = time.perf_counter()
+    for j in range(1, 5):
+        assert o1.pass_(j, 1000) == 0
+    dt1 = time.perf_counter() - t1
     return {"value": round(corpus.nbytes / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "pass n=%d, k_keep=%d over the first %d files of the corpus (%d bytes), after its own passes 1..%d; "
-                      "%.2f s" % (n, k_keep, sample_files, corpus.nbytes, n - 1, dt)}
+                      "%.2f s" % (n, k_keep, sample_files, corpus.nbytes, n - 1, dt),
+            "cpu_model": cpu_model(),
+            "single_thread_tiny": {"GB_per_s_per_pass": round(4 * tiny.nbytes / dt1 / 1e9, 4),
+                                   "sample": "1 thread, 64 files x 64 KiB, passes n=1..4, k_keep=1000, %.2f s" % dt1}}
 
 
 def serve_stream(g, ig, requests, budget, n_streams, max_batch):
@@ -240,7 +281,9 @@ def main():
     log("pass %d: %.3f ms/step wall, device pass %.3f ms, scan %.3f ms, %.1f GB/s" % (
         a.n, ms_per_step, sum(pass_ms) / len(pass_ms), scan_avg, value))
 
-    extra = {"device_pass_ms": round(sum(pass_ms) / len(pass_ms), 4), "scan_ms": round(scan_avg, 4),
+    extra = {"device_pass_ms": round(sum(pass_ms) / len(pass_ms), 4),
+             "device_pass_ms_median": round(sorted(pass_ms)[len(pass_ms) // 2], 4),
+             "scan_ms": round(scan_avg, 4),
              "select_ms": round(st["select_ms"], 4), "windows": st["windows"], "distinct_counted": st["distinct"],
              "split_file_records": st["records"],
              "launch": {"chunk_syms": st["chunk_syms"], "block": st["block"], "grid": st["grid"],
@@ -282,6 +325,8 @@ def main():
         gp.close()
     g_launch = g.launch()
     g.close()
+    extra["hbm_read_attainable"] = hbm_read_attainable()
+    log("attainable HBM read: %s" % extra["hbm_read_attainable"])
     quality = None
     theory_rows = None
     if a.recall_files:
