@@ -166,6 +166,13 @@ typedef struct {
 } ig_pass_stats;
 int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
 
+/* Measurement aid, not part of the method: the read bandwidth (GB/s, 1e9 B) that a plain
+ * streaming kernel attains on ctx's device, for comparison with a pass's input rate.  It
+ * allocates `bytes` (within the context's HBM budget), reads them once untimed and then reps
+ * times timed with device events, and frees them.  Errors: IG_EINVAL (bytes < 16, reps = 0,
+ * null output), IG_ESTATE while serving, IG_ENOMEM, IG_EDEVICE. */
+int  ig_measure_read_bw(ig_ctx *ctx, uint64_t bytes, uint32_t reps, double *gb_per_s);
+
 const char *ig_last_error(const ig_ctx *ctx);
 
 /* ---------------------------------------------------------------------------

@@ -108,6 +108,7 @@ def load_library(path=LIB_PATH):
     lib.ig_pass.argtypes = [vp, u32, u64]
     lib.ig_rewind.argtypes = [vp]
     lib.ig_intergrams.argtypes = [vp, u32, u64, dbl]
+    lib.ig_measure_read_bw.argtypes = [vp, u64, u32, P(dbl)]
     lib.ig_topk.argtypes = [vp, u64, vp, vp, P(u64)]
     lib.ig_table_info.argtypes = [vp, P(u32), P(u64)]
     lib.ig_featurize.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
@@ -271,6 +272,12 @@ class Intergrams:
 
     def set_launch(self, chunk_syms, block, set_cap):
         self._check(self._lib.ig_set_launch(self._h, chunk_syms, block, set_cap))
+
+    def measure_read_bw(self, nbytes=4 << 30, reps=5):
+        """GB/s that the library's plain streaming-read kernel attains on this device."""
+        out = ctypes.c_double()
+        self._check(self._lib.ig_measure_read_bw(self._h, nbytes, reps, ctypes.byref(out)))
+        return out.value
 
     def last_stats(self):
         st = ig_pass_stats()

@@ -186,6 +186,19 @@ def test_many_short_sequences():
     assert_tables_equal(got, exp, "70000 sequences")
 
 
+def test_measure_read_bw():
+    g = ig.Intergrams()
+    try:
+        say("streaming-read bandwidth over 256 MiB")
+        bw = g.measure_read_bw(256 << 20, 3)
+        assert 100.0 < bw < 8000.0 * 1.05, bw   # below the HBM peak
+        with pytest.raises(ig.IGError) as e:
+            g.measure_read_bw(8, 1)
+        assert e.value.code == ig.IG_EINVAL
+    finally:
+        g.close()
+
+
 def test_edge_cases():
     cases = [
         ("empty corpus", [], [1, 2], 10),
