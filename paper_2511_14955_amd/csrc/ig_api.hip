@@ -371,7 +371,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // level-1 histogram: a filtered pass knows its bucket count now (its candidate space is fixed);
   // the other passes assume the largest (256 buckets per wavefront)
   p.hist_words = occ ? 0u : (c->lc.block / 64) * (mode == MODE_FILTERED ? dedup_shape(nc, c->m).nb1 : 256u);
-  p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 8u : 0u;
+  p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 10u : 0u;   // 8 B key + 2 B step
   // without LDS for the survivor rings the scan resolves survivors in place; so it does when
   // the previous table holds every (n-1)-gram over the alphabet (every window survives)
   if (p.qbytes && scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192) p.qbytes = 0;

@@ -210,7 +210,7 @@ struct ScanParams {
   uint32_t *status;
   uint32_t set_cap;              // LDS de-duplication set entries (power of two)
   uint32_t stage_bytes;          // LDS staging bytes
-  uint32_t qbytes;               // LDS bytes of the per-wavefront survivor rings (filtered 64-bit keys)
+  uint32_t qbytes;               // LDS bytes of the per-wavefront survivor rings (keys + displacements)
 };
 
 // Once-per-sequence counting from chunk records (see ig_dedup.hip).

@@ -115,6 +115,9 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   // wavefront (a few hot buckets take most records; a shared copy would serialize them)
   // filtered 64-bit keys: one ring of SCAN_QCAP filter survivors per wavefront
   uint64_t *s_q = reinterpret_cast<uint64_t *>(s_code + 256);
+  // and, after the keys, 16 bits per ring entry: the next displacement to probe (the quotient
+  // map's displacement field has at most 16 bits)
+  uint16_t *s_qd = reinterpret_cast<uint16_t *>(s_q + (size_t)(blockDim.x >> 6) * SCAN_QCAP);
   uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256 + p.qbytes);
   __shared__ uint32_t s_chunk;
 
@@ -215,6 +218,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       // LDS ring instead (ballot + prefix count) and resolved 64 at a time, one per lane.
       constexpr int RBC = 4;
       uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
+      uint16_t *qd = s_qd + (tid >> 6) * SCAN_QCAP;
       const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
       uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
       KeyT<1> k;
@@ -225,28 +229,42 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       // decides (home and stored bits give back the key); otherwise the fingerprinted map and
       // the table's keys are probed.  An empty slot ends either probe.
       const bool useq = p.qmap != nullptr && *p.qflag == 0u;
+      // Each dequeued key takes exactly one probe step (two neighbouring slots).  Slots that hold
+      // other keys send the key back into the ring with the next displacement (a later drain
+      // takes it), so a few displaced keys never hold up the other lanes of the wavefront.
       auto drain = [&](uint32_t cnt) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        bool again = false;
+        uint64_t key = 0;
+        uint32_t dnext = 0;
         if (lane < cnt) {
-          const uint64_t key = q[(head + lane) & (SCAN_QCAP - 1)];
+          key = q[(head + lane) & (SCAN_QCAP - 1)];
+          const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
           const uint64_t plo = key >> B;
           uint32_t cid = LDS_EMPTY;   // not found
           if (useq) {
+            // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
+            // slot 0); a key further out comes back with d+2
             const uint64_t x = qmix(plo, p.qs.w);
-            uint64_t slot = x >> p.qs.qbits;
+            const uint64_t slot = ((x >> p.qs.qbits) + d) & p.mmask;
             const uint64_t rem = p.qs.qbits ? (x & ((1ull << p.qs.qbits) - 1)) : 0ull;
-            uint64_t e = p.qmap[slot];
+            typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2), aligned(8)));
+            const u64x2_t e2 = *reinterpret_cast<const u64x2_t *>(p.qmap + slot);
             const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
             const uint64_t dmax = (1ull << p.qs.dbits) - 1;
             const uint32_t rsh = p.qs.rbits + p.qs.dbits;
-            for (uint64_t d = 0; e != 0;) {
-              if (((e >> p.qs.rbits) & dmax) == d && (e >> rsh) == rem) {
-                cid = (((uint32_t)e & rmask) - 1) * p.sigma + code;
-                break;
+            const uint64_t e0 = e2.x, e1 = e2.y;
+            if (e0 != 0) {
+              if (((e0 >> p.qs.rbits) & dmax) == d && (e0 >> rsh) == rem) {
+                cid = (((uint32_t)e0 & rmask) - 1) * p.sigma + code;
+              } else if (e1 != 0 && d + 1 <= dmax) {
+                if (((e1 >> p.qs.rbits) & dmax) == d + 1 && (e1 >> rsh) == rem) {
+                  cid = (((uint32_t)e1 & rmask) - 1) * p.sigma + code;
+                } else if (d + 2 <= dmax) {
+                  again = true;
+                  dnext = d + 2;
+                }
               }
-              if (++d > dmax) break;
-              slot = (slot + 1) & p.mmask;
-              e = p.qmap[slot];
             }
           } else {
             const uint64_t h = hash_key(plo, 0);
@@ -266,11 +284,18 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               v = p.map[slot];
             }
           }
-          // one insert per lane after the probe, not one per probe step
           if (cid != LDS_EMPTY) handle(cid);
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         head += cnt;
+        // requeue behind the live entries: at most 63 + cnt <= 127 entries are live afterwards
+        const uint64_t m = __ballot(again);
+        if (again) {
+          const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
+          q[at] = key;
+          qd[at] = (uint16_t)dnext;
+        }
+        tail += (uint32_t)__popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       };
       const bool bloom = p.filt_kind == FILT_BLOOM, direct = p.filt_kind == FILT_DIRECT;
       for (uint32_t it = 0; it < per; it += RBC) {
@@ -308,15 +333,19 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         for (int u = 0; u < RBC; u++) {
           const bool sv = pass & 1u;
           const uint64_t m = __ballot(sv);
-          if (sv) q[(tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1)] = kk[0];
+          if (sv) {
+            const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
+            q[at] = kk[0];
+            qd[at] = 0;
+          }
           tail += (uint32_t)__popcll(m);
-          if (tail - head >= 64) drain(64);
+          while (tail - head >= 64) drain(64);
           pass >>= 1;
 #pragma unroll
           for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
         }
       }
-      if (tail != head) drain(tail - head);
+      while (tail != head) drain(tail - head < 64 ? tail - head : 64u);
     } else if (t_lo < t_hi) {
       KeyT<KW> k;
       k.clear();

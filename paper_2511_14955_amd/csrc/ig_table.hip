@@ -59,6 +59,10 @@ __global__ void k_qmap_insert(const uint64_t *tlo, const unsigned long long *kep
   }
 }
 
+__global__ void k_qmap_mirror(unsigned long long *qmap, uint64_t mmask) {
+  if (threadIdx.x == 0) qmap[mmask + 1] = qmap[0];
+}
+
 __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *filt,
                                uint32_t words, uint32_t kind) {
   const uint64_t kept = *kept_p;
@@ -104,7 +108,8 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     const int room = 64 - (int)qs.qbits - (int)qs.rbits;
     if (room >= 6) {
       qs.dbits = room < 16 ? (uint32_t)room : 16u;
-      if (dev_reserve(c, ts.qmap, cap * 8) || dev_reserve(c, ts.qflag, 64)) return IG_ENOMEM;
+      // one slot past the end mirrors slot 0, so that a probe can read two neighbouring slots
+      if (dev_reserve(c, ts.qmap, (cap + 1) * 8) || dev_reserve(c, ts.qflag, 64)) return IG_ENOMEM;
       ts.qs = qs;
       ts.has_qmap = true;
     }
@@ -131,7 +136,7 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
                      reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.filt.p),
                      ts.filt_words, ts.filt_kind);
   if (ts.has_qmap) {
-    if ((e = hipGetLastError()) == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t *>(ts.qmap.p), ts.map_mask + 1, 0, s);
+    if ((e = hipGetLastError()) == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t *>(ts.qmap.p), ts.map_mask + 2, 0, s);
     if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.qflag.p), 1, 0, s);
     if (e != hipSuccess) return e;
     // ranks [0, 256), [256, 1024), [1024, 4096), ... then the rest
@@ -144,6 +149,8 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
                          reinterpret_cast<uint32_t *>(ts.qflag.p), ts.map_mask, ts.qs);
       r0 = r1;
     }
+    hipLaunchKernelGGL(k_qmap_mirror, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(ts.qmap.p),
+                       ts.map_mask);
   }
   return hipGetLastError();
 }
