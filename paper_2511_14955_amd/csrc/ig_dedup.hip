@@ -545,12 +545,26 @@ __global__ void __launch_bounds__(512) k_count(DedupParams d) {
         f1 = Rec<R2>::file(r, d.low2) + 1;
         cl = Rec<R2>::cl(r, d.low2);
       }
-      // lanes holding the same candidate
-      const uint64_t same = wave_match(cl, d.low2, valid);
+      const uint32_t lp = valid ? (NARROW ? (uint32_t)last16[cl] : last[cl]) : 0u;
+      // lanes holding the same candidate: each valid lane writes its lane number into the
+      // candidate's entry and reads back the one that stayed, a lane of its own group, so
+      // matching that 6-bit leader groups the lanes as matching the candidate would.  The
+      // entry gets its sequence back below from the group's highest lane.
+      // (atomic accesses: the read must not be answered from this lane's own write)
+      uint32_t leader = 0;
+      if (valid) {
+        if (NARROW) {
+          __hip_atomic_store(last16 + cl, (uint16_t)lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          leader = __hip_atomic_load(last16 + cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        } else {
+          __hip_atomic_store(last + cl, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+          leader = __hip_atomic_load(last + cl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+      }
+      const uint64_t same = wave_match(leader, 6, valid);
       const uint64_t below = same & lt;
       const uint32_t pred = below ? 63u - (uint32_t)__clzll((unsigned long long)below) : lane;
       const uint32_t fpred = (uint32_t)__shfl((int)f1, (int)pred);
-      const uint32_t lp = valid ? (NARROW ? (uint32_t)last16[cl] : last[cl]) : 0u;
       const bool isnew = valid && (below ? fpred != f1 : lp != f1);
       const bool islast = valid && (same >> lane) == 1ull;   // highest lane of its group
       if (NARROW) {

@@ -81,13 +81,17 @@ __host__ __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t words, u
 // Invalid lanes get the mask of valid lanes sharing their bits, which callers ignore.
 __device__ __forceinline__ uint64_t wave_match(uint32_t key, uint32_t nbits, bool valid) {
   const uint64_t vm = __ballot(valid);
-  uint64_t same = vm;
+  // per bit: the lanes with that bit set, complemented where this lane's bit is clear (an
+  // xor with an all-ones word, so each step is a few plain VALU operations on the ballot)
+  uint32_t lo = (uint32_t)vm, hi = (uint32_t)(vm >> 32);
   for (uint32_t q = 0; q < nbits; q++) {
-    const bool bit = (key >> q) & 1u;
-    const uint64_t bq = __ballot(valid && bit);
-    same &= bit ? bq : (vm & ~bq);
+    const uint32_t bit = (key >> q) & 1u;
+    const uint64_t bq = __ballot(bit != 0u);
+    const uint32_t flip = bit - 1u;   // 0 where the bit is set, all ones where it is clear
+    lo &= (uint32_t)bq ^ flip;
+    hi &= (uint32_t)(bq >> 32) ^ flip;
   }
-  return same;
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Key -> rank map: one 32-bit slot per entry, holding rank+1 in its low rank_bits bits and a
