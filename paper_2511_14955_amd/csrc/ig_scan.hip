@@ -21,6 +21,8 @@
 // their top bits; the records are counted once per sequence afterwards without
 // device-scope atomics (ig_dedup.hip).  A candidate that finds the LDS set full
 // is recorded directly (a duplicate record within one sequence is harmless).
+#include <type_traits>
+
 #include "ig_internal.h"
 
 namespace ig {
@@ -297,54 +299,73 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         tail += (uint32_t)__popcll(m);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       };
-      const bool bloom = p.filt_kind == FILT_BLOOM, direct = p.filt_kind == FILT_DIRECT;
-      for (uint32_t it = 0; it < per; it += RBC) {
-        // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
-        // each issued together: lanes past their last window read a staged symbol in range
-        // and never pass
-        uint64_t kk[RBC];
-        uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
-        uint32_t pass = 0;
+      // Staged position (symbols from the stage's first byte) of the last symbol of this
+      // thread's first window, and of the chunk's last window.  A batch that starts past the
+      // chunk's last window reads at the clamp, at most RBC - 1 symbols into the stage's
+      // padding, and none of its windows passes.
+      const uint32_t g0 = (uint32_t)(wbeg + n - 1 - (B == 8 ? sbase : 4 * sbase)) + (uint32_t)t_lo;
+      const uint32_t gmax = (uint32_t)(wend + n - 2 - (B == 8 ? sbase : 4 * sbase));
+      const uint32_t nmine = t_hi > t_lo ? (uint32_t)(t_hi - t_lo) : 0u;
+      // one copy of the loop per filter kind, so that no window branches on it
+      auto windows = [&](auto kind) {
+        constexpr int FK = decltype(kind)::value;
+        for (uint32_t it = 0; it < per; it += RBC) {
+          // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
+          // each issued together
+          const uint32_t gb = g0 + it < gmax ? g0 + it : gmax;
+          uint64_t kk[RBC];
+          uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
+          uint32_t pass = 0;
 #pragma unroll
-        for (int u = 0; u < RBC; u++) {
-          const uint64_t t = t_lo + it + u;
-          sym[u] = stage_sym<B>(s_stage, wbeg + (t < nwin ? t : nwin - 1) + n - 1, sbase);
-        }
+          for (int u = 0; u < RBC; u++) {
+            const uint32_t g = gb + u;
+            sym[u] = B == 8 ? (uint32_t)s_stage[g] : ((uint32_t)s_stage[g >> 2] >> (6 - 2 * (g & 3))) & 3u;
+          }
 #pragma unroll
-        for (int u = 0; u < RBC; u++) {
-          k.template push<B>(sym[u], mlo, mhi);
-          kk[u] = k.lo;
-          const uint64_t plo = k.lo >> B;
-          if (bloom) {
-            bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
+          for (int u = 0; u < RBC; u++) {
+            k.template push<B>(sym[u], mlo, mhi);
+            kk[u] = k.lo;
+            const uint64_t plo = k.lo >> B;
+            if constexpr (FK == FILT_BLOOM) {
+              bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
+            } else if constexpr (FK == FILT_DIRECT) {
+              widx[u] = (uint32_t)(plo >> 5) & fmask;
+              bm[u] = 1u << (plo & 31);
+            }
+          }
+          if constexpr (FK != FILT_NONE) {
+#pragma unroll
+            for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
+#pragma unroll
+            for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
           } else {
-            widx[u] = direct ? (uint32_t)(plo >> 5) & fmask : 0u;
-            bm[u] = direct ? 1u << (plo & 31) : 0u;
+            pass = (1u << RBC) - 1;
           }
-        }
-#pragma unroll
-        for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
-#pragma unroll
-        for (int u = 0; u < RBC; u++)
-          pass |= (uint32_t)((w[u] & bm[u]) == bm[u] && t_lo + it + u < t_hi) << u;
-        // a rolled loop (the keys shift down one register per step) keeps a single copy of
-        // the drain in the loop body
+          // the windows of this batch that are this thread's
+          pass &= nmine > it ? (nmine - it >= (uint32_t)RBC ? (1u << RBC) - 1 : (1u << (nmine - it)) - 1) : 0u;
+          // a rolled loop (the keys shift down one register per step) keeps a single copy of
+          // the drain in the loop body
 #pragma unroll 1
-        for (int u = 0; u < RBC; u++) {
-          const bool sv = pass & 1u;
-          const uint64_t m = __ballot(sv);
-          if (sv) {
-            const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
-            q[at] = kk[0];
-            qd[at] = 0;
-          }
-          tail += (uint32_t)__popcll(m);
-          while (tail - head >= 64) drain(64);
-          pass >>= 1;
+          for (int u = 0; u < RBC; u++) {
+            const bool sv = pass & 1u;
+            const uint64_t m = __ballot(sv);
+            if (sv) {
+              const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+              const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
+              q[at] = kk[0];
+              qd[at] = 0;
+            }
+            tail += (uint32_t)__popcll(m);
+            while (tail - head >= 64) drain(64);
+            pass >>= 1;
 #pragma unroll
-          for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
+            for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
+          }
         }
-      }
+      };
+      if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
+      else if (p.filt_kind == FILT_DIRECT) windows(std::integral_constant<int, FILT_DIRECT>{});
+      else windows(std::integral_constant<int, FILT_NONE>{});
       while (tail != head) drain(tail - head < 64 ? tail - head : 64u);
     } else if (t_lo < t_hi) {
       KeyT<KW> k;
