@@ -370,6 +370,16 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
   const uint32_t dm = d.nb2 - 1;
   const uint32_t m2 = d.low2 >= 32 ? 0xFFFFFFFFu : ((1u << d.low2) - 1);
   const uint64_t lt = (1ull << lane) - 1;
+  // The next tile's records are loaded into registers while this tile is sorted and written.
+  // Every tile lies inside the padded level-1 array (ntiles * TILE records, at most cap, or the
+  // pass has stopped above), so the loads need no bound; records past a bucket's end are not used.
+  R1 rn[SLICE_ROUNDS];
+  auto load_tile = [&](uint64_t tt) {
+    const uint64_t i0 = tt * TILE + (uint64_t)w * SLICE_ROUNDS * 64 + lane;
+#pragma unroll
+    for (uint32_t q = 0; q < SLICE_ROUNDS; q++) rn[q] = in[i0 + q * 64];
+  };
+  if (blockIdx.x < ntiles) load_tile(blockIdx.x);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcur_[k] = 0;
     __syncthreads();
@@ -379,18 +389,20 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
     const uint64_t hi = pos + TILE < s_bend[b] ? pos + TILE : s_bend[b];
     const uint64_t s0 = pos + (uint64_t)w * SLICE_ROUNDS * 64;
     // per round only the record and its digit-match mask stay in registers (sequence, candidate
-    // and digit are decoded again in the replay), which keeps the kernel under 64 VGPRs
+    // and digit are decoded again in the replay)
+    // (of the digit match only this lane's rank in its group and the group's size are kept)
     R1 rr[SLICE_ROUNDS];
-    uint64_t rs[SLICE_ROUNDS];
+    uint32_t rs[SLICE_ROUNDS];   // rank | size << 8
     // pass 1: this wavefront's digit counts
 #pragma unroll
     for (uint32_t q = 0; q < SLICE_ROUNDS; q++) {
       const uint64_t i = s0 + q * 64 + lane;
       const bool valid = i < hi;
-      rr[q] = valid ? in[i] : (R1)0;
+      rr[q] = valid ? rn[q] : (R1)0;
       const uint32_t rd = (Rec<R1>::cl(rr[q], d.low1) >> d.low2) & dm;
-      rs[q] = wave_match(rd, d.b2bits, valid);
-      if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
+      const uint64_t same = wave_match(rd, d.b2bits, valid);
+      rs[q] = (uint32_t)__popcll(same & lt) | ((uint32_t)__popcll(same) << 8);
+      if (valid && (rs[q] & 0xFFu) == 0) wcur(w, rd) += rs[q] >> 8;
     }
     __syncthreads();
     // per digit: the tile's first position, each wavefront's offset from it, the digit's total
@@ -405,6 +417,9 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
       toff[k] = off;
     }
     __syncthreads();
+    // (issued after this tile's last global loads, the reads of its digit bases above: a wait
+    // for those would otherwise wait for these too)
+    if (t + gridDim.x < ntiles) load_tile(t + gridDim.x);
     // exclusive scan of the digit totals (one wavefront, nb2 / 64 consecutive digits per lane)
     if (w == 0) {
       const uint32_t per = (d.nb2 + 63) / 64, k0 = lane * per, k1 = k0 + per < d.nb2 ? k0 + per : d.nb2;
@@ -430,13 +445,13 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6
       const bool valid = i < hi;
       const uint32_t rc = Rec<R1>::cl(rr[q], d.low1), rd = (rc >> d.low2) & dm;
       if (valid) {
-        const uint32_t slot = toff[rd] + wcur(w, rd) + (uint32_t)__popcll(rs[q] & lt);
+        const uint32_t slot = toff[rd] + wcur(w, rd) + (rs[q] & 0xFFu);
         stage[slot] = Rec<R2>::pack(Rec<R1>::file(rr[q], d.low1), rc & m2, d.low2);
         sdig[slot] = (uint16_t)rd;
       }
       // every lane has read its cursor before the group's first lane advances it
       __builtin_amdgcn_wave_barrier();
-      if (valid && (rs[q] & lt) == 0) wcur(w, rd) += (uint32_t)__popcll(rs[q]);
+      if (valid && (rs[q] & 0xFFu) == 0) wcur(w, rd) += rs[q] >> 8;
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
