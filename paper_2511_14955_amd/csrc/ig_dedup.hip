@@ -36,6 +36,7 @@ namespace ig {
 static constexpr uint32_t TILE = 4096;          // records per level-2 tile
 static constexpr uint32_t SCAN_SEG = 4096;      // elements per block of the generic scan
 static constexpr uint32_t P2_BLOCK = 512;       // threads of the level-2 kernels
+static constexpr uint32_t SLICE_ROUNDS = TILE / P2_BLOCK;   // records per thread and tile in the level-2 kernels
 static constexpr uint32_t NCOL_MAX = 1024;      // chunk groups of the column scan
 static constexpr uint32_t SEG = 32768;          // records per counting segment (buckets are cut into segments)
 static constexpr uint32_t CNT_LDS = 64 * 1024;  // LDS of one count workgroup
@@ -313,10 +314,14 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_hist(DedupParams d) {
     const uint64_t hi = pos + TILE < s_bend[b] ? pos + TILE : s_bend[b];
     for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) h[k] = 0;
     __syncthreads();
-    for (uint64_t i = pos + tid; i < hi; i += P2_BLOCK) {
-      const uint32_t cl = Rec<R1>::cl(in[i], d.low1);
-      atomicAdd(h + ((cl >> d.low2) & dm), 1u);
-    }
+    // the tile's loads are issued together (every tile lies inside the padded level-1 array,
+    // so they need no bound); records past the bucket's end are not counted
+    R1 v[SLICE_ROUNDS];
+#pragma unroll
+    for (uint32_t q = 0; q < SLICE_ROUNDS; q++) v[q] = in[pos + q * P2_BLOCK + tid];
+#pragma unroll
+    for (uint32_t q = 0; q < SLICE_ROUNDS; q++)
+      if (pos + q * P2_BLOCK + tid < hi) atomicAdd(h + ((Rec<R1>::cl(v[q], d.low1) >> d.low2) & dm), 1u);
     __syncthreads();
     for (uint32_t k = tid; k < d.nb2; k += P2_BLOCK) d.hist2[tb * d.nb2 + k * ntb + tl] = h[k];
     __syncthreads();
@@ -343,7 +348,6 @@ __global__ void k_fin(DedupParams d) {
 // kept in registers).  Each wavefront counts its slice's digits, one prefix over the
 // wavefronts (per digit) gives every wavefront its first position, and each wavefront then
 // replays its rounds in order, advancing its own cursors: positions follow the tile order.
-static constexpr uint32_t SLICE_ROUNDS = TILE / P2_BLOCK;   // rounds of 64 per wavefront and tile
 template <typename R1, typename R2>
 __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) k_p2_scatter(DedupParams d) {
   constexpr uint32_t NW = P2_BLOCK / 64;
@@ -650,7 +654,9 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bases, dim3(1), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const uint32_t grid = (uint32_t)n_cu * 4;
+  // 6 workgroups of 4 wavefronts per CU (all resident at its register use): each walks its
+  // chunks one after another, and the others hide the latency of each chunk's first loads
+  const uint32_t grid = (uint32_t)n_cu * 6;
   if (d.w1 == 4) hipLaunchKernelGGL(k_gather<uint32_t>, dim3(grid), dim3(256), 0, s, d);
   else hipLaunchKernelGGL(k_gather<uint64_t>, dim3(grid), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
