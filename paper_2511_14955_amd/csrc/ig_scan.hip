@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   // map's displacement field has at most 16 bits)
   uint16_t *s_qd = reinterpret_cast<uint16_t *>(s_q + (size_t)(blockDim.x >> 6) * SCAN_QCAP);
   uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256 + p.qbytes);
-  __shared__ uint32_t s_chunk;
+  __shared__ uint32_t s_chunk, s_next;
 
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
   const uint32_t n = p.n;
@@ -153,48 +153,88 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     atomicAdd(my_h1 + (p.low1 >= 32 ? 0u : (cid >> p.low1)), 1u);
   };
 
-  uint32_t local_iter = 0;
+  constexpr uint32_t END = 0xFFFFFFFFu;
+  auto valid_chunk = [&](uint32_t ci) {
+    return ci != END && (p.persistent ? ci < p.nchunks : ci < p.chunk_base + p.nchunks);
+  };
+  // a chunk's windows [wbeg, wend) and the 16-byte words [a0, a0 + 16 nw) of the corpus it stages
+  struct Span {
+    Chunk c;
+    uint64_t wbeg, wend, a0;
+    uint32_t nw;
+  };
+  auto span_of = [&](uint32_t ci) {
+    Span sp;
+    sp.c = p.chunks[ci];
+    const uint64_t fend = p.offs[sp.c.file + 1];
+    const uint64_t flen = fend - p.offs[sp.c.file];
+    sp.wbeg = sp.c.s0;
+    sp.wend = sp.c.s0 + sp.c.nsym;
+    if (flen < n) sp.wend = sp.wbeg;
+    else if (sp.wend > fend - n + 1) sp.wend = fend - n + 1;
+    sp.a0 = 0;
+    sp.nw = 0;
+    if (sp.wbeg < sp.wend) {
+      const uint64_t byte_lo = (B == 8) ? sp.wbeg : (sp.wbeg >> 2);
+      const uint64_t byte_hi = (B == 8) ? (sp.wend + n - 1) : ((sp.wend + n - 2) >> 2) + 1;
+      sp.a0 = byte_lo & ~15ull;
+      sp.nw = (uint32_t)((((byte_hi + 15) & ~15ull) - sp.a0) / 16);
+    }
+    return sp;
+  };
+  // The corpus streams through once per pass: non-temporal loads keep it from evicting the
+  // key -> rank map from L2.
+  typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+  auto word_at = [&](const Span &sp, uint32_t i) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(p.data + sp.a0) + i);
+  };
+  // Persistent launches of the compacted kernel run their chunks as a pipeline: the next chunk
+  // is known one chunk ahead (thread 0 claims the one after it while the current chunk runs),
+  // the first PF 16-byte words per thread of its stage load into registers while the current
+  // chunk's windows run, and go to the stage once those are done.
+  constexpr uint32_t PF = CMP != 0 ? 4u : 0u;
+  u32x4_t pf[PF ? PF : 1];
+  if (tid == 0) {
+    uint32_t c0 = END, c1 = END;
+    if (p.persistent) {
+      c0 = atomicAdd(p.qctr, 1u);
+      if (PF) c1 = atomicAdd(p.qctr, 1u);
+    } else {
+      c0 = p.chunk_base + blockIdx.x;
+    }
+    // a table overflowed: this launch will be replayed with larger tables, stop early
+    if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) c0 = c1 = END;
+    s_chunk = c0;
+    s_next = c1;
+  }
+  __syncthreads();
+  Span nx{};             // the next chunk's span (when have_nx)
+  bool have_nx = false;
+  uint32_t staged = 0;   // words of the current chunk already in the stage
   for (;;) {
-    if (tid == 0) {
-      if (p.persistent) s_chunk = atomicAdd(p.qctr, 1u);
-      else s_chunk = local_iter == 0 ? p.chunk_base + blockIdx.x : 0xFFFFFFFFu;
-      // a table overflowed: this launch will be replayed with larger tables, stop early
-      if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) s_chunk = 0xFFFFFFFFu;
+    const uint32_t ci = __builtin_amdgcn_readfirstlane(s_chunk);
+    const uint32_t cn = __builtin_amdgcn_readfirstlane(s_next);
+    if (!valid_chunk(ci)) break;
+    uint32_t claim = END;   // thread 0: the chunk after cn
+    if (PF && tid == 0 && valid_chunk(cn)) claim = atomicAdd(p.qctr, 1u);
+    const Span cur = have_nx ? nx : span_of(ci);
+    const Chunk c = cur.c;
+    const uint64_t wbeg = cur.wbeg, wend = cur.wend;
+    // the rest of this chunk's stage (all of it unless loaded ahead), then the next chunk's
+    // first words into registers
+    for (uint32_t i = staged + tid; i < cur.nw; i += bs) reinterpret_cast<u32x4_t *>(s_stage)[i] = word_at(cur, i);
+    have_nx = false;
+    if (PF && valid_chunk(cn)) {
+      nx = span_of(cn);
+      have_nx = true;
+#pragma unroll
+      for (uint32_t q = 0; q < PF; q++)
+        if (q * bs + tid < nx.nw) pf[q] = word_at(nx, q * bs + tid);
     }
     __syncthreads();
-    const uint32_t ci = s_chunk;
-    local_iter++;
-    if (ci == 0xFFFFFFFFu || (p.persistent ? ci >= p.nchunks : ci >= p.chunk_base + p.nchunks)) break;
-    const Chunk c = p.chunks[ci];
-    const uint64_t fend = p.offs[c.file + 1];
-    const uint64_t flen = fend - p.offs[c.file];
-    const uint64_t wbeg = c.s0;
-    uint64_t wend = c.s0 + c.nsym;
-    if (flen < n) wend = wbeg;
-    else if (wend > fend - n + 1) wend = fend - n + 1;
-    if (wbeg >= wend) {
-      // no window: an Eq. 2 chunk still reports zero records
-      if (!OCC) {
-        if (tid == 0) p.nrec[c.fci] = 0;
-        for (uint32_t b = tid; b < p.nb1; b += bs) p.hist1[(uint64_t)c.fci * p.nb1 + b] = 0;
-      }
-      __syncthreads();
-      continue;
-    }
+    if (wbeg < wend) {
     const uint64_t nwin = wend - wbeg;
-
-    // stage [wbeg, wend + n - 1) symbols with 16-byte loads
-    const uint64_t byte_lo = (B == 8) ? wbeg : (wbeg >> 2);
-    const uint64_t byte_hi = (B == 8) ? (wend + n - 1) : ((wend + n - 2) >> 2) + 1;
-    const uint64_t a0 = byte_lo & ~15ull;
-    const uint64_t a1 = (byte_hi + 15) & ~15ull;
-    const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
-    // the corpus streams through once per pass: non-temporal loads keep it from evicting
-    // the key -> rank map from L2
-    typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-    for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs)
-      reinterpret_cast<u32x4_t *>(s_stage)[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t *>(src) + i);
-    __syncthreads();
+    const uint64_t a0 = cur.a0;
 
     // each thread rolls its key over a contiguous run of windows; an odd run length puts
     // neighbouring lanes' staged symbols in different LDS banks
@@ -461,7 +501,16 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         }
       }
     }
+    }   // a chunk with windows
     __syncthreads();
+    // the stage is free: the next chunk's loaded words go in
+    staged = 0;
+    if (PF && have_nx) {
+#pragma unroll
+      for (uint32_t q = 0; q < PF; q++)
+        if (q * bs + tid < nx.nw) reinterpret_cast<u32x4_t *>(s_stage)[q * bs + tid] = pf[q];
+      staged = nx.nw < PF * bs ? nx.nw : PF * bs;
+    }
     // set_cap is a multiple of the block, so every lane of a wavefront runs the same iterations
     for (uint32_t i = tid; i < p.set_cap; i += bs) {
       const uint32_t cid = s_set[i];
@@ -501,8 +550,20 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         }
         p.hist1[(uint64_t)c.fci * p.nb1 + b] = sum;
       }
-      __syncthreads();
     }
+    if (tid == 0) {
+      uint32_t c0 = END, c1 = END;
+      if (PF) {
+        c0 = cn;
+        c1 = claim;
+      } else if (p.persistent) {
+        c0 = atomicAdd(p.qctr, 1u);
+      }
+      if (__hip_atomic_load(p.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) c0 = c1 = END;
+      s_chunk = c0;
+      s_next = c1;
+    }
+    __syncthreads();
   }
 }
 
