@@ -205,12 +205,14 @@ __global__ void __launch_bounds__(256) k_bases(DedupParams d) {
 }
 
 // ------------------------------------------------------------------ level-1 gather
+static constexpr uint32_t GATHER_BLOCK = 512;
 template <typename R1>
-__global__ void __launch_bounds__(256) k_gather(DedupParams d) {
+__global__ void __launch_bounds__(GATHER_BLOCK) k_gather(DedupParams d) {
   // Records go through LDS in tiles of GT, counting-sorted by bucket, so that consecutive lanes
   // write consecutive positions of one bucket's run (a direct scatter sends each lane of a store
-  // to a different bucket, so to a different cache line).
-  constexpr uint32_t GT = 2048, PER = GT / 256;
+  // to a different bucket, so to a different cache line).  Larger tiles make longer runs: fewer
+  // partly written lines at their ends.
+  constexpr uint32_t GB = GATHER_BLOCK, GT = 4096, PER = GT / GB;
   __shared__ uint64_t s_base[256];   // the chunk's first position in each bucket
   __shared__ uint32_t s_cur[256];    // records of the chunk already written per bucket
   __shared__ uint32_t s_h[256];      // the tile's records per bucket
@@ -238,35 +240,41 @@ __global__ void __launch_bounds__(256) k_gather(DedupParams d) {
     const uint32_t *src = d.rec0 + c.s0;
     for (uint32_t t0 = 0; t0 < n; t0 += GT) {
       const uint32_t m = n - t0 < GT ? n - t0 : GT;
-      s_h[tid] = 0;
+      if (tid < 256) s_h[tid] = 0;
       __syncthreads();
       // this thread's records of the tile (loads first), their buckets and ranks within them
       uint32_t cid[PER], rk[PER];
 #pragma unroll
-      for (uint32_t q = 0; q < PER; q++) cid[q] = src[t0 + (q * 256 + tid < m ? q * 256 + tid : m - 1)];
+      for (uint32_t q = 0; q < PER; q++) cid[q] = src[t0 + (q * GB + tid < m ? q * GB + tid : m - 1)];
 #pragma unroll
       for (uint32_t q = 0; q < PER; q++)
-        rk[q] = q * 256 + tid < m ? atomicAdd(s_h + bucket(cid[q]), 1u) : 0u;
+        rk[q] = q * GB + tid < m ? atomicAdd(s_h + bucket(cid[q]), 1u) : 0u;
       __syncthreads();
-      // exclusive scan of the tile's bucket counts (one bucket per thread)
-      const uint32_t hv = s_h[tid];
-      uint32_t x = hv;
-      for (uint32_t off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
+      // exclusive scan of the tile's bucket counts (one bucket per thread of the first four
+      // wavefronts)
+      uint32_t hv = 0, x = 0;
+      if (tid < 256) {
+        hv = s_h[tid];
+        x = hv;
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+          const uint32_t y = __shfl_up(x, off);
+          if (lane >= off) x += y;
+        }
+        if (lane == 63) s_wsum[w] = x;
       }
-      if (lane == 63) s_wsum[w] = x;
       __syncthreads();
-      uint32_t wb = 0;
-      for (uint32_t ww = 0; ww < w; ww++) wb += s_wsum[ww];
-      s_off[tid] = wb + x - hv;
+      if (tid < 256) {
+        uint32_t wb = 0;
+        for (uint32_t ww = 0; ww < w; ww++) wb += s_wsum[ww];
+        s_off[tid] = wb + x - hv;
+      }
       __syncthreads();
 #pragma unroll
       for (uint32_t q = 0; q < PER; q++)
-        if (q * 256 + tid < m) s_stage[s_off[bucket(cid[q])] + rk[q]] = cid[q];
+        if (q * GB + tid < m) s_stage[s_off[bucket(cid[q])] + rk[q]] = cid[q];
       __syncthreads();
       // sorted slots: slot j of bucket b goes to the chunk's run in b
-      for (uint32_t j = tid; j < m; j += 256) {
+      for (uint32_t j = tid; j < m; j += GB) {
         const uint32_t v = s_stage[j];
         const uint32_t b = bucket(v);
         const uint64_t at = s_base[b] + s_cur[b] + (j - s_off[b]);
@@ -654,11 +662,11 @@ hipError_t dedup_enqueue(const DedupParams &d, int n_cu, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bases, dim3(1), dim3(256), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // 6 workgroups of 4 wavefronts per CU (all resident at its register use): each walks its
-  // chunks one after another, and the others hide the latency of each chunk's first loads
-  const uint32_t grid = (uint32_t)n_cu * 6;
-  if (d.w1 == 4) hipLaunchKernelGGL(k_gather<uint32_t>, dim3(grid), dim3(256), 0, s, d);
-  else hipLaunchKernelGGL(k_gather<uint64_t>, dim3(grid), dim3(256), 0, s, d);
+  // 4 workgroups of 8 wavefronts per CU (all resident at its register and LDS use): each walks
+  // its chunks one after another, and the others hide the latency of each chunk's first loads
+  const uint32_t grid = (uint32_t)n_cu * 4;
+  if (d.w1 == 4) hipLaunchKernelGGL(k_gather<uint32_t>, dim3(grid), dim3(GATHER_BLOCK), 0, s, d);
+  else hipLaunchKernelGGL(k_gather<uint64_t>, dim3(grid), dim3(GATHER_BLOCK), 0, s, d);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t g2 = (uint32_t)n_cu * 4;
   if (d.w1 == 4) hipLaunchKernelGGL(k_p2_hist<uint32_t>, dim3(g2), dim3(P2_BLOCK), 0, s, d);
