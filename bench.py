@@ -131,10 +131,15 @@ def serve_stream(g, ig, requests, budget, n_streams, max_batch):
     its latency runs from that arrival to its row being on the host."""
     import gen
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     rs = gen.RequestStream()
-    files = [rs.file(i) for i in range(requests)]
+    t_gen = time.time()
+    # every request is a pure function of its index: generated by a pool of host threads
+    with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+        files = list(ex.map(rs.file, range(requests), chunksize=64))
     gaps = np.array([rs.gap(i) for i in range(requests)])
     nbytes = int(sum(len(f) for f in files))
+    log("serving: %d requests generated (%.2f GB) in %.1f s" % (requests, nbytes / 1e9, time.time() - t_gen))
     offs = [np.array([0, len(f)], np.uint64) for f in files]
     g.serve_start(max_inflight_bytes=budget, n_streams=n_streams, max_batch=max_batch, queue_capacity=1 << 20)
     t0 = g.serve_now() + 0.01
@@ -149,6 +154,8 @@ def serve_stream(g, ig, requests, budget, n_streams, max_batch):
             rc = g.submit(ig.REQ_FEATURIZE, files[i], offs[i], tag=i, t_arrival=float(arrive[i]))
             assert rc == ig.IG_OK, rc
             i += 1
+            if i % 20000 == 0:
+                log("serving: %d of %d requests submitted" % (i, requests))
             now = g.serve_now()
         for r in g.poll():
             got[r["tag"]] = r
