@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--launch", default=None, help="fixed scan launch shape CHUNK,BLOCK,SETCAP (no autotune)")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only stream BYTES through a plain device copy kernel 5 times (counter calibration)")
-    ap.add_argument("--serve-requests", type=int, default=4000, help="requests replayed from the stream (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=100000, help="requests replayed from the stream (0: skip)")
     ap.add_argument("--recall-files", type=int, default=1024, help="files of the recall sample (0: skip)")
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving HBM budget in bytes")
     ap.add_argument("--serve-streams", type=int, default=4)
