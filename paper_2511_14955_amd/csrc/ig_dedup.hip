@@ -356,8 +356,10 @@ __global__ void k_fin(DedupParams d) {
 // kept in registers).  Each wavefront counts its slice's digits, one prefix over the
 // wavefronts (per digit) gives every wavefront its first position, and each wavefront then
 // replays its rounds in order, advancing its own cursors: positions follow the tile order.
+// (Registers for 5 wavefronts per SIMD: the tile in flight and the next one's records fit
+// without spills, and 2 workgroups per CU are resident.)
 template <typename R1, typename R2>
-__global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(6))) k_p2_scatter(DedupParams d) {
+__global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_p2_scatter(DedupParams d) {
   constexpr uint32_t NW = P2_BLOCK / 64;
   __shared__ uint64_t s_base1[257];
   __shared__ uint64_t s_bend[256];
