@@ -233,275 +233,276 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     }
     __syncthreads();
     if (wbeg < wend) {
-    const uint64_t nwin = wend - wbeg;
-    const uint64_t a0 = cur.a0;
+      const uint64_t nwin = wend - wbeg;
+      const uint64_t a0 = cur.a0;
 
-    // each thread rolls its key over a contiguous run of windows; an odd run length puts
-    // neighbouring lanes' staged symbols in different LDS banks
-    const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;
-    const uint64_t t_lo = (uint64_t)tid * per;
-    const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
-    const uint64_t sbase = a0;
-    // one surviving candidate: de-duplicate in the chunk's LDS set
-    auto handle = [&](uint32_t cid) {
-      uint32_t slot;
-      const int ins = lds_insert(s_set, capmask, capshift, cid, &slot);
-      if (OCC) {
-        if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
-        else cnt_add<CT>(p.cnt, cid, (CT)1);
-      } else if (ins < 0) {
-        emit(wbeg, cid);
-      }
-    };
-    if constexpr (CMP != 0) {
-      // About a third of the windows pass the filter, so nearly every wavefront has a
-      // survivor at each step: resolving survivors in place would run the probe on all 64
-      // lanes for a few live ones.  Survivors' keys are compacted into the wavefront's
-      // LDS ring instead (ballot + prefix count) and resolved 64 at a time, one per lane.
-      constexpr int RBC = 4;
-      uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
-      uint16_t *qd = s_qd + (tid >> 6) * SCAN_QCAP;
-      const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
-      uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
-      KeyT<1> k;
-      k.clear();
-      if (t_lo < t_hi)
-        for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, wbeg + t_lo + r, sbase), mlo, mhi);
-      // Exact rank of each queued key's prefix.  With the quotient map one 8-byte slot read
-      // decides (home and stored bits give back the key); otherwise the fingerprinted map and
-      // the table's keys are probed.  An empty slot ends either probe.
-      const bool useq = p.qmap != nullptr && *p.qflag == 0u;
-      // Each dequeued key takes exactly one probe step (two neighbouring slots).  Slots that hold
-      // other keys send the key back into the ring with the next displacement (a later drain
-      // takes it), so a few displaced keys never hold up the other lanes of the wavefront.
-      auto drain = [&](uint32_t cnt) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        bool again = false;
-        uint64_t key = 0;
-        uint32_t dnext = 0;
-        if (lane < cnt) {
-          key = q[(head + lane) & (SCAN_QCAP - 1)];
-          const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
-          const uint64_t plo = key >> B;
-          uint32_t cid = LDS_EMPTY;   // not found
-          if (useq) {
-            // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
-            // slot 0); a key further out comes back with d+2
-            const uint64_t x = qmix(plo, p.qs.w);
-            const uint64_t slot = ((x >> p.qs.qbits) + d) & p.mmask;
-            const uint64_t rem = p.qs.qbits ? (x & ((1ull << p.qs.qbits) - 1)) : 0ull;
-            typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2), aligned(8)));
-            const u64x2_t e2 = *reinterpret_cast<const u64x2_t *>(p.qmap + slot);
-            const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
-            const uint64_t dmax = (1ull << p.qs.dbits) - 1;
-            const uint32_t rsh = p.qs.rbits + p.qs.dbits;
-            const uint64_t e0 = e2.x, e1 = e2.y;
-            if (e0 != 0) {
-              if (((e0 >> p.qs.rbits) & dmax) == d && (e0 >> rsh) == rem) {
-                cid = (((uint32_t)e0 & rmask) - 1) * p.sigma + code;
-              } else if (e1 != 0 && d + 1 <= dmax) {
-                if (((e1 >> p.qs.rbits) & dmax) == d + 1 && (e1 >> rsh) == rem) {
-                  cid = (((uint32_t)e1 & rmask) - 1) * p.sigma + code;
-                } else if (d + 2 <= dmax) {
-                  again = true;
-                  dnext = d + 2;
-                }
-              }
-            }
-          } else {
-            const uint64_t h = hash_key(plo, 0);
-            const uint32_t fp = map_fp(h, p.rank_bits);
-            uint64_t slot = h & p.mmask;
-            uint32_t v = p.map[slot];
-            const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
-            while (v != 0) {
-              if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
-                const uint32_t r = (v & rmask) - 1;
-                if (p.tkeys_lo[r] == plo) {
-                  cid = r * p.sigma + code;
-                  break;
-                }
-              }
-              slot = (slot + 1) & p.mmask;
-              v = p.map[slot];
-            }
-          }
-          if (cid != LDS_EMPTY) handle(cid);
-        }
-        head += cnt;
-        // requeue behind the live entries: at most 63 + cnt <= 127 entries are live afterwards
-        const uint64_t m = __ballot(again);
-        if (again) {
-          const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
-          q[at] = key;
-          qd[at] = (uint16_t)dnext;
-        }
-        tail += (uint32_t)__popcll(m);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      };
-      // Staged position (symbols from the stage's first byte) of the last symbol of this
-      // thread's first window, and of the chunk's last window.  A batch that starts past the
-      // chunk's last window reads at the clamp, at most RBC - 1 symbols into the stage's
-      // padding, and none of its windows passes.
-      const uint32_t g0 = (uint32_t)(wbeg + n - 1 - (B == 8 ? sbase : 4 * sbase)) + (uint32_t)t_lo;
-      const uint32_t gmax = (uint32_t)(wend + n - 2 - (B == 8 ? sbase : 4 * sbase));
-      const uint32_t nmine = t_hi > t_lo ? (uint32_t)(t_hi - t_lo) : 0u;
-      // one copy of the loop per filter kind, so that no window branches on it
-      auto windows = [&](auto kind) {
-        constexpr int FK = decltype(kind)::value;
-        for (uint32_t it = 0; it < per; it += RBC) {
-          // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
-          // each issued together
-          const uint32_t gb = g0 + it < gmax ? g0 + it : gmax;
-          uint64_t kk[RBC];
-          uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
-          uint32_t pass = 0;
-#pragma unroll
-          for (int u = 0; u < RBC; u++) {
-            const uint32_t g = gb + u;
-            sym[u] = B == 8 ? (uint32_t)s_stage[g] : ((uint32_t)s_stage[g >> 2] >> (6 - 2 * (g & 3))) & 3u;
-          }
-#pragma unroll
-          for (int u = 0; u < RBC; u++) {
-            k.template push<B>(sym[u], mlo, mhi);
-            kk[u] = k.lo;
-            const uint64_t plo = k.lo >> B;
-            if constexpr (FK == FILT_BLOOM) {
-              bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
-            } else if constexpr (FK == FILT_DIRECT) {
-              widx[u] = (uint32_t)(plo >> 5) & fmask;
-              bm[u] = 1u << (plo & 31);
-            }
-          }
-          if constexpr (FK != FILT_NONE) {
-#pragma unroll
-            for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
-#pragma unroll
-            for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
-          } else {
-            pass = (1u << RBC) - 1;
-          }
-          // the windows of this batch that are this thread's
-          pass &= nmine > it ? (nmine - it >= (uint32_t)RBC ? (1u << RBC) - 1 : (1u << (nmine - it)) - 1) : 0u;
-          // a rolled loop (the keys shift down one register per step) keeps a single copy of
-          // the drain in the loop body
-#pragma unroll 1
-          for (int u = 0; u < RBC; u++) {
-            const bool sv = pass & 1u;
-            const uint64_t m = __ballot(sv);
-            if (sv) {
-              const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-              const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
-              q[at] = kk[0];
-              qd[at] = 0;
-            }
-            tail += (uint32_t)__popcll(m);
-            while (tail - head >= 64) drain(64);
-            pass >>= 1;
-#pragma unroll
-            for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
-          }
+      // each thread rolls its key over a contiguous run of windows; an odd run length puts
+      // neighbouring lanes' staged symbols in different LDS banks
+      const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;
+      const uint64_t t_lo = (uint64_t)tid * per;
+      const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
+      const uint64_t sbase = a0;
+      // one surviving candidate: de-duplicate in the chunk's LDS set
+      auto handle = [&](uint32_t cid) {
+        uint32_t slot;
+        const int ins = lds_insert(s_set, capmask, capshift, cid, &slot);
+        if (OCC) {
+          if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
+          else cnt_add<CT>(p.cnt, cid, (CT)1);
+        } else if (ins < 0) {
+          emit(wbeg, cid);
         }
       };
-      if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
-      else if (p.filt_kind == FILT_DIRECT) windows(std::integral_constant<int, FILT_DIRECT>{});
-      else windows(std::integral_constant<int, FILT_NONE>{});
-      while (tail != head) drain(tail - head < 64 ? tail - head : 64u);
-    } else if (t_lo < t_hi) {
-      KeyT<KW> k;
-      k.clear();
-      const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
-      for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
-      if (MODE == MODE_FILTERED) {
-        // Windows are taken RB at a time: every window's key is rolled and filtered and the
-        // first map slot of each survivor is read; then the keys of fingerprint matches are
-        // read from the table; then the probes are resolved.  Up to RB independent reads
-        // per thread are in flight at each step.
-        constexpr int RB = KW == 2 ? 4 : 8;   // 128-bit keys: half the batch, no register spills
+      if constexpr (CMP != 0) {
+        // About a third of the windows pass the filter, so nearly every wavefront has a
+        // survivor at each step: resolving survivors in place would run the probe on all 64
+        // lanes for a few live ones.  Survivors' keys are compacted into the wavefront's
+        // LDS ring instead (ballot + prefix count) and resolved 64 at a time, one per lane.
+        constexpr int RBC = 4;
+        uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
+        uint16_t *qd = s_qd + (tid >> 6) * SCAN_QCAP;
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
-        for (uint64_t t0 = t_lo; t0 < t_hi; t0 += RB) {
-          // q_*[u] are only read where bit u of `live` (or `hit`) is set
-          uint64_t q_lo[RB], q_hi[RB], q_klo[RB], q_khi[RB], q_slot[RB];
-          uint32_t q_v[RB], q_fp[RB], q_code[RB];
-          uint32_t live = 0, hit = 0;
-#pragma unroll
-          for (int u = 0; u < RB; u++) {
-            if (t0 + u >= t_hi) continue;
-            const uint64_t g = wbeg + t0 + u;
-            k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
-            const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
-            uint64_t h = 0;
-            if (p.filt_kind == FILT_DIRECT) {
-              if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
-            } else if (p.filt_kind == FILT_BLOOM) {
-              uint32_t wi, bm;
-              bloom_pos(bloom_fold(plo, phi), p.filt_words, &wi, &bm);
-              const uint32_t w = s_filt[wi];
-              if ((w & bm) != bm) continue;
-            }
-            h = hash_key(plo, phi);
-            const uint64_t slot = h & p.mmask;
-            q_slot[u] = slot;
-            q_v[u] = p.map[slot];
-            q_fp[u] = map_fp(h, p.rank_bits);
-            q_lo[u] = plo;
-            q_hi[u] = phi;
-            q_code[u] = s_code[(uint32_t)(k.lo & ((1u << B) - 1))];
-            live |= 1u << u;
-          }
-#pragma unroll
-          for (int u = 0; u < RB; u++) {
-            if (!((live >> u) & 1u)) continue;
-            const uint32_t v = q_v[u];
-            if (v != 0 && (p.rank_bits >= 32 || (v >> p.rank_bits) == q_fp[u])) {
-              const uint32_t r = (v & rmask) - 1;
-              q_klo[u] = p.tkeys_lo[r];
-              if (KW == 2) q_khi[u] = p.tkeys_hi[r];
-              hit |= 1u << u;
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < RB; u++) {
-            if (!((live >> u) & 1u)) continue;
-            uint64_t slot = q_slot[u];
-            uint32_t v = q_v[u];
-            int64_t r = -1;
-            if (((hit >> u) & 1u) && q_klo[u] == q_lo[u] && (KW == 1 || q_khi[u] == q_hi[u])) {
-              r = (int64_t)(v & rmask) - 1;
+        uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
+        KeyT<1> k;
+        k.clear();
+        if (t_lo < t_hi)
+          for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, wbeg + t_lo + r, sbase), mlo, mhi);
+        // Exact rank of each queued key's prefix.  With the quotient map one 8-byte slot read
+        // decides (home and stored bits give back the key); otherwise the fingerprinted map and
+        // the table's keys are probed.  An empty slot ends either probe.
+        const bool useq = p.qmap != nullptr && *p.qflag == 0u;
+        // Each dequeued key takes exactly one probe step (two neighbouring slots).  Slots that hold
+        // other keys send the key back into the ring with the next displacement (a later drain
+        // takes it), so a few displaced keys never hold up the other lanes of the wavefront.
+        auto drain = [&](uint32_t cnt) {
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          bool again = false;
+          uint64_t key = 0;
+          uint32_t dnext = 0;
+          if (lane < cnt) {
+            key = q[(head + lane) & (SCAN_QCAP - 1)];
+            const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
+            const uint64_t plo = key >> B;
+            uint32_t cid = LDS_EMPTY;   // not found
+            if (useq) {
+              // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
+              // slot 0); a key further out comes back with d+2
+              const uint64_t x = qmix(plo, p.qs.w);
+              const uint64_t slot = ((x >> p.qs.qbits) + d) & p.mmask;
+              const uint64_t rem = p.qs.qbits ? (x & ((1ull << p.qs.qbits) - 1)) : 0ull;
+              typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2), aligned(8)));
+              const u64x2_t e2 = *reinterpret_cast<const u64x2_t *>(p.qmap + slot);
+              const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
+              const uint64_t dmax = (1ull << p.qs.dbits) - 1;
+              const uint32_t rsh = p.qs.rbits + p.qs.dbits;
+              const uint64_t e0 = e2.x, e1 = e2.y;
+              if (e0 != 0) {
+                if (((e0 >> p.qs.rbits) & dmax) == d && (e0 >> rsh) == rem) {
+                  cid = (((uint32_t)e0 & rmask) - 1) * p.sigma + code;
+                } else if (e1 != 0 && d + 1 <= dmax) {
+                  if (((e1 >> p.qs.rbits) & dmax) == d + 1 && (e1 >> rsh) == rem) {
+                    cid = (((uint32_t)e1 & rmask) - 1) * p.sigma + code;
+                  } else if (d + 2 <= dmax) {
+                    again = true;
+                    dnext = d + 2;
+                  }
+                }
+              }
             } else {
-              // rare: the first slot was another key's; continue the linear probe
+              const uint64_t h = hash_key(plo, 0);
+              const uint32_t fp = map_fp(h, p.rank_bits);
+              uint64_t slot = h & p.mmask;
+              uint32_t v = p.map[slot];
+              const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
               while (v != 0) {
+                if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
+                  const uint32_t r = (v & rmask) - 1;
+                  if (p.tkeys_lo[r] == plo) {
+                    cid = r * p.sigma + code;
+                    break;
+                  }
+                }
                 slot = (slot + 1) & p.mmask;
                 v = p.map[slot];
-                if (v == 0) break;
-                if (p.rank_bits < 32 && (v >> p.rank_bits) != q_fp[u]) continue;
-                const uint32_t rr = (v & rmask) - 1;
-                if (p.tkeys_lo[rr] == q_lo[u] && (KW == 1 || p.tkeys_hi[rr] == q_hi[u])) {
-                  r = rr;
-                  break;
-                }
               }
             }
-            if (r < 0) continue;
-            handle((uint32_t)r * p.sigma + q_code[u]);
+            if (cid != LDS_EMPTY) handle(cid);
           }
-        }
-      } else {
-        for (uint64_t t = t_lo; t < t_hi; t++) {
-          const uint64_t g = wbeg + t;
-          k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
-          uint32_t cid;
-          if (MODE == MODE_DENSE) {
-            cid = (uint32_t)k.lo;
-          } else {
-            cid = table_insert(p, k.lo, k.hi);
-            if (cid == 0xFFFFFFFFu) continue;
+          head += cnt;
+          // requeue behind the live entries: at most 63 + cnt <= 127 entries are live afterwards
+          const uint64_t m = __ballot(again);
+          if (again) {
+            const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
+            q[at] = key;
+            qd[at] = (uint16_t)dnext;
           }
-          handle(cid);
+          tail += (uint32_t)__popcll(m);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        };
+        // Staged position (symbols from the stage's first byte) of the last symbol of this
+        // thread's first window, and of the chunk's last window.  A batch that starts past the
+        // chunk's last window reads at the clamp, at most RBC - 1 symbols into the stage's
+        // padding, and none of its windows passes.
+        const uint32_t g0 = (uint32_t)(wbeg + n - 1 - (B == 8 ? sbase : 4 * sbase)) + (uint32_t)t_lo;
+        const uint32_t gmax = (uint32_t)(wend + n - 2 - (B == 8 ? sbase : 4 * sbase));
+        const uint32_t nmine = t_hi > t_lo ? (uint32_t)(t_hi - t_lo) : 0u;
+        // one copy of the loop per filter kind, so that no window branches on it
+        auto windows = [&](auto kind) {
+          constexpr int FK = decltype(kind)::value;
+          for (uint32_t it = 0; it < per; it += RBC) {
+            // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
+            // each issued together
+            const uint32_t gb = g0 + it < gmax ? g0 + it : gmax;
+            uint64_t kk[RBC];
+            uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
+            uint32_t pass = 0;
+#pragma unroll
+            for (int u = 0; u < RBC; u++) {
+              const uint32_t g = gb + u;
+              sym[u] = B == 8 ? (uint32_t)s_stage[g] : ((uint32_t)s_stage[g >> 2] >> (6 - 2 * (g & 3))) & 3u;
+            }
+#pragma unroll
+            for (int u = 0; u < RBC; u++) {
+              k.template push<B>(sym[u], mlo, mhi);
+              kk[u] = k.lo;
+              const uint64_t plo = k.lo >> B;
+              if constexpr (FK == FILT_BLOOM) {
+                bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
+              } else if constexpr (FK == FILT_DIRECT) {
+                widx[u] = (uint32_t)(plo >> 5) & fmask;
+                bm[u] = 1u << (plo & 31);
+              }
+            }
+            if constexpr (FK != FILT_NONE) {
+#pragma unroll
+              for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
+#pragma unroll
+              for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
+            } else {
+              pass = (1u << RBC) - 1;
+            }
+            // the windows of this batch that are this thread's
+            pass &= nmine > it ? (nmine - it >= (uint32_t)RBC ? (1u << RBC) - 1 : (1u << (nmine - it)) - 1) : 0u;
+            // a rolled loop (the keys shift down one register per step) keeps a single copy of
+            // the drain in the loop body
+#pragma unroll 1
+            for (int u = 0; u < RBC; u++) {
+              const bool sv = pass & 1u;
+              const uint64_t m = __ballot(sv);
+              if (sv) {
+                const uint32_t below =
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
+                q[at] = kk[0];
+                qd[at] = 0;
+              }
+              tail += (uint32_t)__popcll(m);
+              while (tail - head >= 64) drain(64);
+              pass >>= 1;
+#pragma unroll
+              for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
+            }
+          }
+        };
+        if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
+        else if (p.filt_kind == FILT_DIRECT) windows(std::integral_constant<int, FILT_DIRECT>{});
+        else windows(std::integral_constant<int, FILT_NONE>{});
+        while (tail != head) drain(tail - head < 64 ? tail - head : 64u);
+      } else if (t_lo < t_hi) {
+        KeyT<KW> k;
+        k.clear();
+        const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
+        for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
+        if (MODE == MODE_FILTERED) {
+          // Windows are taken RB at a time: every window's key is rolled and filtered and the
+          // first map slot of each survivor is read; then the keys of fingerprint matches are
+          // read from the table; then the probes are resolved.  Up to RB independent reads
+          // per thread are in flight at each step.
+          constexpr int RB = KW == 2 ? 4 : 8;   // 128-bit keys: half the batch, no register spills
+          const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
+          for (uint64_t t0 = t_lo; t0 < t_hi; t0 += RB) {
+            // q_*[u] are only read where bit u of `live` (or `hit`) is set
+            uint64_t q_lo[RB], q_hi[RB], q_klo[RB], q_khi[RB], q_slot[RB];
+            uint32_t q_v[RB], q_fp[RB], q_code[RB];
+            uint32_t live = 0, hit = 0;
+#pragma unroll
+            for (int u = 0; u < RB; u++) {
+              if (t0 + u >= t_hi) continue;
+              const uint64_t g = wbeg + t0 + u;
+              k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
+              const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
+              uint64_t h = 0;
+              if (p.filt_kind == FILT_DIRECT) {
+                if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
+              } else if (p.filt_kind == FILT_BLOOM) {
+                uint32_t wi, bm;
+                bloom_pos(bloom_fold(plo, phi), p.filt_words, &wi, &bm);
+                const uint32_t w = s_filt[wi];
+                if ((w & bm) != bm) continue;
+              }
+              h = hash_key(plo, phi);
+              const uint64_t slot = h & p.mmask;
+              q_slot[u] = slot;
+              q_v[u] = p.map[slot];
+              q_fp[u] = map_fp(h, p.rank_bits);
+              q_lo[u] = plo;
+              q_hi[u] = phi;
+              q_code[u] = s_code[(uint32_t)(k.lo & ((1u << B) - 1))];
+              live |= 1u << u;
+            }
+#pragma unroll
+            for (int u = 0; u < RB; u++) {
+              if (!((live >> u) & 1u)) continue;
+              const uint32_t v = q_v[u];
+              if (v != 0 && (p.rank_bits >= 32 || (v >> p.rank_bits) == q_fp[u])) {
+                const uint32_t r = (v & rmask) - 1;
+                q_klo[u] = p.tkeys_lo[r];
+                if (KW == 2) q_khi[u] = p.tkeys_hi[r];
+                hit |= 1u << u;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < RB; u++) {
+              if (!((live >> u) & 1u)) continue;
+              uint64_t slot = q_slot[u];
+              uint32_t v = q_v[u];
+              int64_t r = -1;
+              if (((hit >> u) & 1u) && q_klo[u] == q_lo[u] && (KW == 1 || q_khi[u] == q_hi[u])) {
+                r = (int64_t)(v & rmask) - 1;
+              } else {
+                // rare: the first slot was another key's; continue the linear probe
+                while (v != 0) {
+                  slot = (slot + 1) & p.mmask;
+                  v = p.map[slot];
+                  if (v == 0) break;
+                  if (p.rank_bits < 32 && (v >> p.rank_bits) != q_fp[u]) continue;
+                  const uint32_t rr = (v & rmask) - 1;
+                  if (p.tkeys_lo[rr] == q_lo[u] && (KW == 1 || p.tkeys_hi[rr] == q_hi[u])) {
+                    r = rr;
+                    break;
+                  }
+                }
+              }
+              if (r < 0) continue;
+              handle((uint32_t)r * p.sigma + q_code[u]);
+            }
+          }
+        } else {
+          for (uint64_t t = t_lo; t < t_hi; t++) {
+            const uint64_t g = wbeg + t;
+            k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
+            uint32_t cid;
+            if (MODE == MODE_DENSE) {
+              cid = (uint32_t)k.lo;
+            } else {
+              cid = table_insert(p, k.lo, k.hi);
+              if (cid == 0xFFFFFFFFu) continue;
+            }
+            handle(cid);
+          }
         }
       }
     }
-    }   // a chunk with windows
     __syncthreads();
     // the stage is free: the next chunk's loaded words go in
     staged = 0;
