@@ -36,9 +36,9 @@ def scan_sources_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(n, launch):
-    """HBM bytes per scan launch from the committed PMC record for this kernel source and launch
-    shape (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), else None."""
+def profiled_record(n, launch):
+    """The committed PMC record for this scan source and launch shape, and its file, else
+    (None, None)."""
     import glob
     import re
     dig = scan_sources_digest()
@@ -49,8 +49,27 @@ def profiled_traffic(n, launch):
             rec = json.loads(block)
             if (rec.get("kernel") == "k_scan" and rec.get("n") == n and rec.get("scan_sources_sha256") == dig
                     and list(rec.get("launch", [])) == list(launch)):
-                return rec["traffic_bytes_per_launch"], os.path.relpath(path, ROOT)
+                return rec, os.path.relpath(path, ROOT)
     return None, None
+
+
+def profiled_traffic(n, launch):
+    """HBM bytes per scan launch from the committed PMC record for this kernel source and launch
+    shape (FETCH_SIZE and WRITE_SIZE, each scaled by a copy kernel's reading), else None."""
+    rec, path = profiled_record(n, launch)
+    return (rec["traffic_bytes_per_launch"], path) if rec else (None, None)
+
+
+def valu_issue(rec, scan_ms):
+    """VALU issue time of one scan launch from the record's SQ_INSTS_VALU (wavefront instructions,
+    4 cycles each on one of 256 x 4 SIMDs at 2.4 GHz), beside the measured launch time."""
+    if not rec or not rec.get("sq_insts_valu") or not scan_ms:
+        return None
+    issue_ms = rec["sq_insts_valu"] * 4.0 / (256 * 4 * 2.4e9) * 1e3
+    return {"valu_wave_instructions": rec["sq_insts_valu"], "issue_ms": round(issue_ms, 3),
+            "frac_of_launch": round(issue_ms / scan_ms, 3),
+            "note": "share of the scan's time its SIMDs spend issuing vector ALU instructions (SQ_INSTS_VALU of "
+                    "the profiled launch); the rest is waiting on L2 and LDS"}
 
 
 def recall_sample(ig, n, k_keep, corpus, zs=(1.0, 1.5, 2.0)):
@@ -353,9 +372,10 @@ def main():
         "extra": extra,
     }
     lc = g_launch
-    traffic, tsrc = profiled_traffic(a.n, [lc["chunk_syms"], lc["block"], lc["set_cap"]])
-    out["roofline"]["traffic"] = traffic
+    rec, tsrc = profiled_record(a.n, [lc["chunk_syms"], lc["block"], lc["set_cap"]])
+    out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] if rec else None
     out["roofline"]["traffic_source"] = tsrc
+    out["roofline"]["valu_issue"] = valu_issue(rec, scan_avg)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(a.n, a.k, a.cpu_sample_files, threads)
         log("cpu baseline: %s" % out["cpu_baseline"])
