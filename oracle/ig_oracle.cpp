@@ -5,10 +5,10 @@
 // baseline do.  It shares no code, header or table with the HIP library.
 //
 // It is deliberately plain: every window's key is rebuilt from its symbols,
-// membership and de-duplication use std::unordered_set, counts use
-// std::unordered_map, and selection is one std::sort.  Threads only split the
-// files between private maps that are summed afterwards (sums commute, so the
-// result does not depend on the split).
+// membership uses std::unordered_set, a sequence's grams are made distinct by
+// sorting them (Eq. 2), counts use std::unordered_map, and selection is one
+// std::sort.  Threads only split the files between private maps that are
+// summed afterwards (sums commute, so the result does not depend on the split).
 //
 // What it computes (arXiv 2511.14955):
 //  * Problem statement (Section "Problem Formalization and Notation"):
@@ -81,7 +81,7 @@ struct Oracle {
 // symbol t of a stream: a byte, or 2 bits taken most significant first
 inline uint32_t symbol(const uint8_t *data, int bits, uint64_t g) {
   if (bits == 8) return data[g];
-  uint32_t per = 8 / (uint32_t)bits;
+  const uint64_t per = 4;      // bits == 2 (the only other width igo_create accepts)
   uint32_t shift = 8 - (uint32_t)bits * (uint32_t)(g % per + 1);
   return (data[g / per] >> shift) & ((1u << bits) - 1);
 }
@@ -122,33 +122,56 @@ int do_pass(Oracle *o, uint32_t n, uint64_t k_keep) {
   const std::vector<uint64_t> ord = file_order(c);
   std::atomic<uint64_t> next(0);
   const int T = std::max(1, o->nthreads);
-  std::vector<CountMap> part(T);
+  // part[t][q]: what thread t counted of the grams in share q (a share is a slice of the hash
+  // range), so that the sums over threads can be taken one share per thread
+  std::vector<std::vector<CountMap>> part(T, std::vector<CountMap>(T));
+  auto share = [&](const u128 &x) { return (int)((KeyHash()(x) >> 40) % (uint64_t)T); };
   auto worker = [&](int tid) {
-    CountMap &cnt = part[tid];
+    std::vector<CountMap> &cnt = part[tid];
+    std::vector<u128> grams;
     for (;;) {
       uint64_t j = next.fetch_add(1);
       if (j >= ord.size()) break;
       uint64_t f = ord[j];
       uint64_t a = c.off[f], L = c.off[f + 1] - a;
       if (L < n) continue;                       // no window fits in this sequence
-      KeySet seen;                               // grams already counted for this sequence (Eq. 2)
+      grams.clear();                             // the accepted grams of this sequence, one per window
       for (uint64_t t = 0; t + n <= L; t++) {
         u128 x = key_at(c.data.data(), o->bits, a + t, n);
         if (filtered && P.find(x >> o->bits) == P.end()) continue;
-        if (!o->occ && !seen.insert(x).second) continue;
-        cnt[x] += 1;
+        grams.push_back(x);
       }
+      if (!o->occ) {                             // Eq. 2: a gram counts once per sequence
+        std::sort(grams.begin(), grams.end());
+        grams.erase(std::unique(grams.begin(), grams.end()), grams.end());
+      }
+      for (const u128 &x : grams) cnt[share(x)][x] += 1;
     }
   };
   std::vector<std::thread> th;
   for (int t = 1; t < T; t++) th.emplace_back(worker, t);
   worker(0);
   for (auto &x : th) x.join();
+  th.clear();
 
-  CountMap total;
-  for (auto &p : part) { for (auto &kv : p) total[kv.first] += kv.second; CountMap().swap(p); }
-  std::vector<std::pair<u128, uint64_t>> all(total.begin(), total.end());
-  CountMap().swap(total);
+  // c(x) = the sum over threads of their counts of x; thread q sums share q
+  std::vector<std::vector<std::pair<u128, uint64_t>>> sums(T);
+  auto summer = [&](int q) {
+    CountMap total;
+    for (int t = 0; t < T; t++) {
+      for (auto &kv : part[t][q]) total[kv.first] += kv.second;
+      CountMap().swap(part[t][q]);
+    }
+    sums[q].assign(total.begin(), total.end());
+  };
+  for (int q = 1; q < T; q++) th.emplace_back(summer, q);
+  summer(0);
+  for (auto &x : th) x.join();
+  std::vector<std::pair<u128, uint64_t>> all;
+  for (auto &v : sums) {
+    all.insert(all.end(), v.begin(), v.end());
+    std::vector<std::pair<u128, uint64_t>>().swap(v);
+  }
   std::sort(all.begin(), all.end(), ranks_before);
   if (all.size() > k_keep) all.resize(k_keep);
   o->R.swap(all);

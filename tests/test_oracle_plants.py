@@ -22,7 +22,7 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 PLANTS = {
     "last_window_dropped": ("for (uint64_t t = 0; t + n <= L; t++) {", "for (uint64_t t = 0; t + n < L; t++) {"),
-    "no_per_sequence_dedup": ("if (!o->occ && !seen.insert(x).second) continue;", "if (false && !seen.insert(x).second) continue;"),
+    "no_per_sequence_dedup": ("if (!o->occ) {", "if (false) {"),
     "ties_key_descending": ("return a.first < b.first;", "return a.first > b.first;"),
     "filter_on_suffix": ("P.find(x >> o->bits)", "P.find(x & ((((u128)1) << (o->bits * (n - 1))) - 1))"),
     "windows_cross_files": ("uint64_t a = c.off[f], L = c.off[f + 1] - a;", "uint64_t a = c.off[f], L = c.off.back() - a;"),
