@@ -179,9 +179,10 @@ const char *ig_last_error(const ig_ctx *ctx);
  * Launch shape of the scan and its autotuner.
  *
  * chunk_syms: symbols per work item (a chunk of one sequence plus its n-1
- * symbol halo); block: threads per workgroup (256, 512, 1024); set_cap: LDS
- * de-duplication set entries (power of two).  The shape changes speed only,
- * never results.
+ * symbol halo, 1024..65536); block: threads per workgroup (256, 512, 1024);
+ * set_cap: LDS de-duplication set entries (a power of two, 1024..32768, at
+ * least block).  IG_EINVAL otherwise.  The shape changes speed only, never
+ * results.
  *
  * ig_autotune runs pass n on the loaded corpus for each candidate shape
  * (rewinding after each), checks that all candidates return the same table,

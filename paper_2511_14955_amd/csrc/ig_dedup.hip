@@ -547,7 +547,10 @@ __global__ void __launch_bounds__(512) k_count(DedupParams d) {
     const uint64_t size = hi > lo ? hi - lo : 0;
     const uint64_t a = snap_to_sequence(in, lo, hi, lo + size * j / nseg, d.low2);
     const uint64_t b = snap_to_sequence(in, lo, hi, lo + size * (j + 1) / nseg, d.low2);
-    if (nseg > 1 && a >= b) continue;   // one sequence spans this cut: the neighbouring segment has it
+    // nothing to count: an empty bucket (its counters were zero-filled before the scan), or one
+    // sequence spans this cut and the neighbouring segment has it.  Skipping here also keeps
+    // the clamped ring loads below inside [a, b).
+    if (a >= b) continue;
     if (NARROW) {
       for (uint32_t k = lane; k < cb; k += 64) last16[k] = 0;
       for (uint32_t k = lane; k < cb / 2; k += 64) cnt2[k] = 0;

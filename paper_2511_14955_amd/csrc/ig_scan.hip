@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
-  uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? p.filt_words : 0);
+  // the filter image is padded to 16 bytes, so that the 8-byte ring entries below stay aligned
+  uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? ((p.filt_words + 3u) & ~3u) : 0);
   uint32_t *s_cnt = s_set + p.set_cap;                 // OCC only
   uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
   // Eq. 2: histogram of this chunk's records over the level-1 buckets, one copy per
@@ -570,7 +571,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
 
 size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
   size_t b = p.stage_bytes;
-  if (mode == MODE_FILTERED) b += (size_t)p.filt_words * 4;
+  if (mode == MODE_FILTERED) b += (size_t)((p.filt_words + 3u) & ~3u) * 4;
   b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
   b += 256;
   b += p.qbytes;

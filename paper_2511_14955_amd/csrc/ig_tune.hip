@@ -26,6 +26,14 @@ static std::string tune_key(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   return buf;
 }
 
+// A launch shape the scan supports: whole wavefronts per workgroup, a power-of-two LDS set of at
+// least one slot per thread (the set's hashing and its flush assume both), chunk length in range.
+static bool shape_ok(uint32_t chunk_syms, uint32_t block, uint32_t set_cap) {
+  return chunk_syms >= 1024 && chunk_syms <= 65536 && (block == 256 || block == 512 || block == 1024) &&
+         set_cap >= 1024 && set_cap <= 32768 && (set_cap & (set_cap - 1)) == 0 && set_cap >= block;
+}
+
+// The last line for `key` whose shape is valid (a stale or edited line is ignored).
 static bool cache_lookup(const std::string &key, LaunchCfg *lc) {
   const char *path = getenv("IG_TUNE_CACHE");
   if (!path) return false;
@@ -36,7 +44,7 @@ static bool cache_lookup(const std::string &key, LaunchCfg *lc) {
   while (fgets(line, sizeof line, f)) {
     char k[600];
     unsigned cs, bl, sc;
-    if (sscanf(line, "%599s %u %u %u", k, &cs, &bl, &sc) == 4 && key == k) {
+    if (sscanf(line, "%599s %u %u %u", k, &cs, &bl, &sc) == 4 && key == k && shape_ok(cs, bl, sc)) {
       lc->chunk_syms = cs;
       lc->block = bl;
       lc->set_cap = sc;
@@ -186,9 +194,7 @@ extern "C" int ig_get_launch(const ig_ctx *c, uint32_t *chunk_syms, uint32_t *bl
 extern "C" int ig_set_launch(ig_ctx *c, uint32_t chunk_syms, uint32_t block, uint32_t set_cap) {
   if (!c) return IG_EINVAL;
   if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
-  if (chunk_syms < 1024 || chunk_syms > 65536 || (block != 256 && block != 512 && block != 1024) || set_cap < 1024 ||
-      set_cap > 32768 || (set_cap & (set_cap - 1)))
-    return set_error(c, IG_EINVAL, "bad launch shape");
+  if (!shape_ok(chunk_syms, block, set_cap)) return set_error(c, IG_EINVAL, "bad launch shape");
   const bool rechunk = chunk_syms != c->lc.chunk_syms;
   c->lc.chunk_syms = chunk_syms;
   c->lc.block = block;

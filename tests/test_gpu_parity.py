@@ -265,3 +265,27 @@ def test_hbm_budget():
     got, gb = gpu_tables(corpus, [1, 2, 3, 4], 1000, ctx=ig.Intergrams(hbm_budget=256 << 20))
     assert_tables_equal(got, exp, "budget")
     gb.close()
+
+
+def test_fresh_dense_pass_with_empty_first_bucket():
+    """A fresh (unfiltered, directly indexed) Eq. 2 pass on printable text: no 2-gram starts
+    with a byte below 0x0A, so the lowest candidate buckets hold no record at all."""
+    corpus = gen.workload(3, m=40)
+    say("fresh dense n=2 and n=3 on the first 40 text documents (empty low buckets)")
+    for ns in ([2], [2, 3], [3]):
+        exp, _ = oracle_tables(corpus, ns, 5000)
+        got, g = gpu_tables(corpus, ns, 5000)
+        g.close()
+        assert_tables_equal(got, exp, "fresh dense %s" % ns)
+
+
+def test_2bit_kept_below_alphabet():
+    """2-bit symbols with fewer kept 1-grams than symbols: the next passes filter by a one-word
+    direct bitmap, and the survivor rings start right after it."""
+    corpus = gen.workload(4, m=4)
+    for k in (1, 2, 3):
+        say("2-bit chain n=1..6 keeping %d" % k)
+        exp, _ = oracle_tables(corpus, [1, 2, 3, 4, 5, 6], k)
+        got, g = gpu_tables(corpus, [1, 2, 3, 4, 5, 6], k)
+        g.close()
+        assert_tables_equal(got, exp, "2-bit k=%d" % k)
