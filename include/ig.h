@@ -140,6 +140,22 @@ int  ig_featurize(ig_ctx *ctx, const void *data, uint64_t data_bytes,
                   const uint64_t *sym_offsets, uint64_t m,
                   uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * or harnesses that forbid hipMalloc): the same rows as ig_featurize, with the same arguments
+ * and errors, computed without allocating.  Every device buffer the call needs beyond its
+ * inputs and outputs (the staged batch, its chunk list, per-sequence rank bitmaps, row counts
+ * and offsets, the CSR entries before their copy out) is carved from a fixed scratch array of
+ * IG_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on until the process
+ * ends.  IG_EINVAL (with a message naming the limit) when a batch does not fit it: about
+ * data_bytes + 24 B per chunk of the launch shape + m * (4 * ceil(kept / 32) + 16) + 4 * nnz
+ * bytes, each piece rounded up to 256.  Calls on one device share that array; within a
+ * process they are serialized (a call waits for the one running on the same device).
+ * IG_EDEVICE if the array could not be located when the context was created. */
+#define IG_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int  ig_featurize_noalloc(ig_ctx *ctx, const void *data, uint64_t data_bytes,
+                          const uint64_t *sym_offsets, uint64_t m,
+                          uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out);
+
 /* The same Boolean rows (Figure 1's m x k matrix) for the m loaded sequences themselves,
  * from the corpus already resident on the device (no host copy of the data).
  *  indptr:  host array of m+1 entries; indices: host array of cap entries (may be NULL

@@ -21,6 +21,7 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "ig.h")
 IG_OK, IG_EINVAL, IG_ESTATE, IG_ENOMEM, IG_ETRUNC, IG_EOVERFLOW, IG_EDEVICE, IG_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
 FREQ_DOC, FREQ_OCC = 0, 1
 FLAG_NO_GRAPH, FLAG_PER_FILE = 1, 2
+NOALLOC_SCRATCH_BYTES = 64 << 20   # IG_NOALLOC_SCRATCH_BYTES
 REQ_FEATURIZE, REQ_COUNT = 0, 1
 
 _ERRNAMES = {IG_EINVAL: "IG_EINVAL", IG_ESTATE: "IG_ESTATE", IG_ENOMEM: "IG_ENOMEM", IG_ETRUNC: "IG_ETRUNC",
@@ -113,6 +114,7 @@ def load_library(path=LIB_PATH):
     lib.ig_table_info.argtypes = [vp, P(u32), P(u64)]
     lib.ig_featurize.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
     lib.ig_featurize_loaded.argtypes = [vp, P(u64), vp, u64, P(u64)]
+    lib.ig_featurize_noalloc.argtypes = [vp, vp, u64, P(u64), u64, P(u64), vp, u64, P(u64)]
     lib.ig_last_pass_stats.argtypes = [vp, P(ig_pass_stats)]
     lib.ig_last_error.argtypes = [vp]
     lib.ig_last_error.restype = ctypes.c_char_p
@@ -226,7 +228,10 @@ class Intergrams:
         keys, counts = self.topk()
         return [(int(lo) | (int(hi) << 64), int(c)) for (lo, hi), c in zip(keys, counts)]
 
-    def featurize(self, corpus_or_data, offsets=None):
+    def featurize(self, corpus_or_data, offsets=None, noalloc=False):
+        """CSR rows (indptr uint64[m+1], indices int32[nnz]) of new sequences; ``noalloc`` calls
+        ig_featurize_noalloc (same rows, no device allocation)."""
+        fn = self._lib.ig_featurize_noalloc if noalloc else self._lib.ig_featurize
         data, offs = _as_host(corpus_or_data, offsets)
         data = np.ascontiguousarray(data, np.uint8)
         m = len(offs) - 1

@@ -188,6 +188,10 @@ int ig_create(const ig_config *cfg, ig_ctx **out) {
   }
   for (auto &e : c->ev)
     if (hipEventCreate(&e) != hipSuccess) { delete c; return IG_EDEVICE; }
+  if (noalloc_setup(c) != IG_OK) {
+    ig_destroy(c);
+    return IG_EDEVICE;
+  }
   if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->code, 256) ||
       dev_reserve(c, c->sym_of_code, 256)) {
     ig_destroy(c);
@@ -707,10 +711,20 @@ int ig_topk(ig_ctx *c, uint64_t k, ig_key *keys, uint64_t *counts, uint64_t *k_o
   return IG_OK;
 }
 
+}  // extern "C"
+
+namespace ig {
+
+static int arena_full(ig_ctx *c, const Carve &a, const char *what) {
+  return set_error(c, IG_EINVAL, "%s does not fit the %llu-byte no-allocation scratch (%llu bytes in use)", what,
+                   (unsigned long long)a.size, (unsigned long long)a.used);
+}
+
 // Boolean rows of a batch already on the device (corpus, offsets, chunks): per-sequence bitmaps
-// of kept ranks, then CSR.
+// of kept ranks, then CSR.  Device buffers come from dev_reserve, or (arena != nullptr) are carved
+// from a region the caller provides, in which case nothing is allocated.
 static int featurize_rows(ig_ctx *c, const FeatBatch &in, uint64_t *indptr, int32_t *indices, uint64_t cap,
-                          uint64_t *nnz_out) {
+                          uint64_t *nnz_out, Carve *arena) {
   hipStream_t s = c->stream;
   const uint64_t m = in.m;
   const uint32_t words = (uint32_t)((c->kept + 31) / 32);
@@ -719,8 +733,14 @@ static int featurize_rows(ig_ctx *c, const FeatBatch &in, uint64_t *indptr, int3
     (void)hipStreamSynchronize(s);
     dev_release(c, d_bm); dev_release(c, d_nnz); dev_release(c, d_ind); dev_release(c, d_ptr);
   };
-  if (dev_reserve(c, d_bm, std::max<uint64_t>(1, m * words) * 4) || dev_reserve(c, d_nnz, std::max<uint64_t>(1, m) * 8) ||
-      dev_reserve(c, d_ptr, (m + 1) * 8)) {
+  const size_t bm_bytes = std::max<uint64_t>(1, m * words) * 4;
+  if (arena) {
+    d_bm.p = arena->take(bm_bytes);
+    d_nnz.p = arena->take(std::max<uint64_t>(1, m) * 8);
+    d_ptr.p = arena->take((m + 1) * 8);
+    if (!d_bm.p || !d_nnz.p || !d_ptr.p) return arena_full(c, *arena, "the row bitmaps");
+  } else if (dev_reserve(c, d_bm, bm_bytes) || dev_reserve(c, d_nnz, std::max<uint64_t>(1, m) * 8) ||
+             dev_reserve(c, d_ptr, (m + 1) * 8)) {
     cleanup();
     return IG_ENOMEM;
   }
@@ -742,7 +762,13 @@ static int featurize_rows(ig_ctx *c, const FeatBatch &in, uint64_t *indptr, int3
   if (total > cap) { cleanup(); return set_error(c, IG_ETRUNC, "need %llu indices", (unsigned long long)total); }
   if (total) {
     if (!indices) { cleanup(); return set_error(c, IG_EINVAL, "null indices"); }
-    if (dev_reserve(c, d_ind, total * 4)) { cleanup(); return IG_ENOMEM; }
+    if (arena) {
+      d_ind.p = arena->take(total * 4);
+      if (!d_ind.p) return arena_full(c, *arena, "the row entries");
+    } else if (dev_reserve(c, d_ind, total * 4)) {
+      cleanup();
+      return IG_ENOMEM;
+    }
     e = hipMemcpyAsync(d_ptr.p, indptr, (m + 1) * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = launch_rows(fb.bitmaps, m, words, nullptr, reinterpret_cast<const uint64_t *>(d_ptr.p),
@@ -751,12 +777,15 @@ static int featurize_rows(ig_ctx *c, const FeatBatch &in, uint64_t *indptr, int3
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (check_hip(c, e, "featurize rows")) { cleanup(); return IG_EDEVICE; }
   }
+  if (arena) return IG_OK;   // nothing was reserved
   cleanup();
   return IG_OK;
 }
 
-int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
-                 uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
+// ig_featurize's body: stage the host batch on the device (from dev_reserve, or carved from
+// `arena`), then the rows.
+int featurize_host(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
+                   uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out, Carve *arena) {
   if (!c) return IG_EINVAL;
   if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
   if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
@@ -780,22 +809,44 @@ int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_
     (void)hipStreamSynchronize(s);
     dev_release(c, d_data); dev_release(c, d_offs); dev_release(c, d_ch);
   };
+  // whole 16-byte words plus 64 zero bytes, so that staging past the last symbol reads zeros
   const uint64_t alloc = ((need + 15) & ~15ull) + 64;
-  if (dev_reserve(c, d_data, alloc) || dev_reserve(c, d_offs, (m + 1) * 8) ||
-      dev_reserve(c, d_ch, std::max<size_t>(1, ch.size()) * sizeof(Chunk))) {
+  const size_t ch_bytes = std::max<size_t>(1, ch.size()) * sizeof(Chunk);
+  if (arena) {
+    d_data.p = arena->take(alloc);
+    d_offs.p = arena->take((m + 1) * 8);
+    d_ch.p = arena->take(ch_bytes);
+    if (!d_data.p || !d_offs.p || !d_ch.p) return arena_full(c, *arena, "the batch");
+  } else if (dev_reserve(c, d_data, alloc) || dev_reserve(c, d_offs, (m + 1) * 8) || dev_reserve(c, d_ch, ch_bytes)) {
     cleanup();
     return IG_ENOMEM;
   }
-  hipError_t e = hipMemsetAsync(reinterpret_cast<uint8_t *>(d_data.p) + need, 0, alloc - need, s);
+  // the zero tail by a fill kernel (the region's last whole word onward; the copy rewrites its head)
+  const uint64_t tail0 = need & ~3ull;
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(d_data.p) + tail0),
+                                 (alloc - tail0) / 4, 0, s);
   if (e == hipSuccess && need) e = hipMemcpyAsync(d_data.p, data, need, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(d_offs.p, sym_offsets, (m + 1) * 8, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && !ch.empty()) e = hipMemcpyAsync(d_ch.p, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, s);
   if (check_hip(c, e, "featurize staging")) { cleanup(); return IG_EDEVICE; }
   FeatBatch fb{reinterpret_cast<const uint8_t *>(d_data.p), reinterpret_cast<const uint64_t *>(d_offs.p), m,
                reinterpret_cast<const Chunk *>(d_ch.p), (uint32_t)ch.size(), nullptr, 0};
-  const int rc = featurize_rows(c, fb, indptr, indices, cap, nnz_out);
+  const int rc = featurize_rows(c, fb, indptr, indices, cap, nnz_out, arena);
+  if (arena) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
   cleanup();
   return rc;
+}
+
+}  // namespace ig
+
+extern "C" {
+
+int ig_featurize(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
+                 uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
+  return featurize_host(c, data, data_bytes, sym_offsets, m, indptr, indices, cap, nnz_out, nullptr);
 }
 
 int ig_featurize_loaded(ig_ctx *c, uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out) {
@@ -808,7 +859,7 @@ int ig_featurize_loaded(ig_ctx *c, uint64_t *indptr, int32_t *indices, uint64_t 
   // the corpus, its offsets and its chunk list are resident since the load
   FeatBatch fb{reinterpret_cast<const uint8_t *>(c->data.p), reinterpret_cast<const uint64_t *>(c->offs.p), c->m,
                reinterpret_cast<const Chunk *>(c->chunks_file.p), (uint32_t)c->nchunks, nullptr, 0};
-  return featurize_rows(c, fb, indptr, indices, cap, nnz_out);
+  return featurize_rows(c, fb, indptr, indices, cap, nnz_out, nullptr);
 }
 
 }  // extern "C"

@@ -392,6 +392,22 @@ struct FeatBatch {
   uint32_t words;
 };
 hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s);
+// A device region that buffers are carved from instead of allocated (256-byte aligned pieces).
+struct Carve {
+  uint8_t *base = nullptr;
+  size_t size = 0, used = 0;
+  void *take(size_t bytes) {
+    const size_t at = (used + 255) & ~(size_t)255;
+    if (bytes > size || at > size - bytes) return nullptr;
+    used = at + bytes;
+    return base + at;
+  }
+};
+// the no-allocation scratch's device address for c's device, taken once per device (ig_noalloc.hip)
+int noalloc_setup(ig_ctx *c);
+// ig_featurize of a host batch; device buffers come from `arena` when it is not null (ig_api.hip)
+int featurize_host(ig_ctx *c, const void *data, uint64_t data_bytes, const uint64_t *sym_offsets, uint64_t m,
+                   uint64_t *indptr, int32_t *indices, uint64_t cap, uint64_t *nnz_out, Carve *arena);
 hipError_t launch_rows(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint64_t *nnz_per_row,
                        const uint64_t *indptr, int32_t *indices, uint64_t cap, int count_only, hipStream_t s);
 hipError_t launch_col_counts(const uint32_t *bitmaps, uint64_t m, uint32_t words, uint32_t kept,
