@@ -202,14 +202,20 @@ const char *ig_last_error(const ig_ctx *ctx);
  *
  * ig_autotune runs pass n on the loaded corpus for each candidate shape
  * (rewinding after each), checks that all candidates return the same table,
- * and keeps the fastest; the chain state is left as it was.  With the
+ * and keeps the fastest; the chain state is left as it was.  It searches the
+ * launch shape first, then, with the best one, the table sizes of
+ * ig_set_tables (map_slots_log2 1 or 2, filter_max_words 8192 or 16384),
+ * which apply to the current table's index.  With the
  * environment variable IG_TUNE_CACHE naming a file, results are read from and
  * appended to it, keyed by device, corpus shape and (n, k_keep).
  * --------------------------------------------------------------------------- */
 #define IG_TUNE_MAX 32
 typedef struct {
   uint32_t n_candidates;
-  struct { uint32_t chunk_syms, block, set_cap; double pass_ms; } cand[IG_TUNE_MAX];  /* pass_ms < 0: shape unusable */
+  struct {
+    uint32_t chunk_syms, block, set_cap, map_slots_log2, filter_max_words;
+    double pass_ms;             /* < 0: shape unusable for this pass */
+  } cand[IG_TUNE_MAX];
   uint32_t best;
   int      identical;     /* 1 if every candidate produced the same table */
   int      from_cache;
@@ -217,6 +223,36 @@ typedef struct {
 int ig_autotune(ig_ctx *ctx, uint32_t n, uint64_t k_keep, ig_tune_report *rep);
 int ig_get_launch(const ig_ctx *ctx, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap);
 int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set_cap);
+
+/* ---------------------------------------------------------------------------
+ * Table sizes (speed only, never results).
+ *
+ *  map_slots_log2:      the exact maps over a retained table of k keys (key -> rank, and the
+ *                       quotient map) get the smallest power of two >= k << map_slots_log2
+ *                       slots: load at most 1/2, 1/4, 1/8 for 1, 2, 3 (default 1).
+ *  filter_bits_per_key: the Bloom filter image a scan workgroup holds in LDS gets about this
+ *                       many bits per retained key (4..32, default 12), a power of two of at
+ *                       most filter_max_words 32-bit words (1024..16384, default 16384).
+ *  sparse_slots:        key-table slots of unfiltered passes with n*b > 26 (a power of two,
+ *                       1024..2^31; 0 leaves it as is; the library starts at twice the windows
+ *                       of the first such pass).  A pass that fills it is replayed with 4x.
+ *  record_capacity:     Eq. 2 records the bucketed arrays hold (0 leaves it as is; raised to
+ *                       one tile per level-1 bucket at least).  A pass that fills it is
+ *                       replayed with twice as much.
+ * ig_set_tables indexes the current table again with the new map and filter sizes, so the
+ * next pass uses them.  IG_EINVAL for values out of range, IG_ESTATE while serving.
+ * ig_autotune also searches map_slots_log2 and filter_max_words (after the launch shape).
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  uint32_t map_slots_log2;
+  uint32_t filter_bits_per_key;
+  uint32_t filter_max_words;
+  uint32_t reserved;
+  uint64_t sparse_slots;
+  uint64_t record_capacity;
+} ig_table_shape;
+int ig_get_tables(const ig_ctx *ctx, ig_table_shape *shape);
+int ig_set_tables(ig_ctx *ctx, const ig_table_shape *shape);
 
 /* ---------------------------------------------------------------------------
  * Serving (continuous batching of featurize / count requests).

@@ -53,7 +53,13 @@ class ig_pass_stats(ctypes.Structure):
 
 class _tune_cand(ctypes.Structure):
     _fields_ = [("chunk_syms", ctypes.c_uint32), ("block", ctypes.c_uint32), ("set_cap", ctypes.c_uint32),
-                ("pass_ms", ctypes.c_double)]
+                ("map_slots_log2", ctypes.c_uint32), ("filter_max_words", ctypes.c_uint32), ("pass_ms", ctypes.c_double)]
+
+
+class ig_table_shape(ctypes.Structure):
+    _fields_ = [("map_slots_log2", ctypes.c_uint32), ("filter_bits_per_key", ctypes.c_uint32),
+                ("filter_max_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("sparse_slots", ctypes.c_uint64), ("record_capacity", ctypes.c_uint64)]
 
 
 IG_TUNE_MAX = 32
@@ -121,6 +127,8 @@ def load_library(path=LIB_PATH):
     lib.ig_autotune.argtypes = [vp, u32, u64, P(ig_tune_report)]
     lib.ig_get_launch.argtypes = [vp, P(u32), P(u32), P(u32)]
     lib.ig_set_launch.argtypes = [vp, u32, u32, u32]
+    lib.ig_get_tables.argtypes = [vp, P(ig_table_shape)]
+    lib.ig_set_tables.argtypes = [vp, P(ig_table_shape)]
     lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
     lib.ig_submit.argtypes = [vp, i32, vp, u64, P(u64), u64, u64, dbl]
     lib.ig_poll.argtypes = [vp, P(ig_result), u64, vp, vp, u64, vp, P(u64)]
@@ -240,8 +248,8 @@ class Intergrams:
         cap = 1 << 16
         while True:
             ind = np.zeros(max(cap, 1), np.int32)
-            rc = self._lib.ig_featurize(self._h, data.ctypes.data, data.nbytes, _u64p(offs), m, _u64p(indptr),
-                                        ind.ctypes.data, cap, ctypes.byref(nnz))
+            rc = fn(self._h, data.ctypes.data, data.nbytes, _u64p(offs), m, _u64p(indptr), ind.ctypes.data, cap,
+                    ctypes.byref(nnz))
             if rc == IG_ETRUNC:
                 cap = int(nnz.value)
                 continue
@@ -265,7 +273,8 @@ class Intergrams:
         """Search the scan's launch shape on pass n (chain state unchanged); returns a report dict."""
         rep = ig_tune_report()
         self._check(self._lib.ig_autotune(self._h, n, k_keep, ctypes.byref(rep)))
-        cands = [{"chunk_syms": c.chunk_syms, "block": c.block, "set_cap": c.set_cap, "pass_ms": c.pass_ms}
+        cands = [{"chunk_syms": c.chunk_syms, "block": c.block, "set_cap": c.set_cap,
+                  "map_slots_log2": c.map_slots_log2, "filter_max_words": c.filter_max_words, "pass_ms": c.pass_ms}
                  for c in rep.cand[:rep.n_candidates]]
         return {"candidates": cands, "best": cands[rep.best] if cands else None, "identical": bool(rep.identical),
                 "from_cache": bool(rep.from_cache)}
@@ -277,6 +286,21 @@ class Intergrams:
 
     def set_launch(self, chunk_syms, block, set_cap):
         self._check(self._lib.ig_set_launch(self._h, chunk_syms, block, set_cap))
+
+    def tables(self):
+        """The table sizes (ig_get_tables) as a dict."""
+        t = ig_table_shape()
+        self._check(self._lib.ig_get_tables(self._h, ctypes.byref(t)))
+        return {f: int(getattr(t, f)) for f, _ in ig_table_shape._fields_ if f != "reserved"}
+
+    def set_tables(self, **kw):
+        """Change some table sizes (ig_set_tables); the others keep their current values
+        (sparse_slots and record_capacity default to 0: left as they are)."""
+        cur = self.tables()
+        cur["sparse_slots"] = cur["record_capacity"] = 0
+        cur.update(kw)
+        t = ig_table_shape(**cur)
+        self._check(self._lib.ig_set_tables(self._h, ctypes.byref(t)))
 
     def measure_read_bw(self, nbytes=4 << 30, reps=5):
         """GB/s that the library's plain streaming-read kernel attains on this device."""

@@ -192,7 +192,8 @@ int ig_create(const ig_config *cfg, ig_ctx **out) {
     ig_destroy(c);
     return IG_EDEVICE;
   }
-  if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->code, 256) ||
+  if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->kdev, 64) ||
+      dev_reserve(c, c->code, 256) ||
       dev_reserve(c, c->sym_of_code, 256)) {
     ig_destroy(c);
     return IG_ENOMEM;
@@ -210,11 +211,11 @@ void ig_destroy(ig_ctx *c) {
       if (x) (void)hipGraphExecDestroy(x);
   c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
-                    &c->status, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
+                    &c->status, &c->kdev, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
-    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map, &t.filt};
+    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map, &t.filt, &t.qmap, &t.qflag};
     for (DevBuf *b : tb) dev_release(c, *b);
   }
   for (auto &e : c->ev)
@@ -416,7 +417,9 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     if (!occ) {
       sh = dedup_shape(nc, c->m);
       const uint64_t floor_cap = ((uint64_t)sh.nb1 + 1) * T;
-      if (c->rec_cap < floor_cap) {
+      if (c->rec_cap < floor_cap && c->rec_floor) {
+        c->rec_cap = (floor_cap + T - 1) / T * T;
+      } else if (c->rec_cap < floor_cap) {
         const uint64_t guess = std::min<uint64_t>(std::max<uint64_t>(W, 1), std::max<uint64_t>(1ull << 22, W / 4));
         c->rec_cap = (guess + floor_cap + T - 1) / T * T;
       }
@@ -796,6 +799,7 @@ int featurize_host(ig_ctx *c, const void *data, uint64_t data_bytes, const uint6
   const uint32_t b = c->cfg.symbol_bits;
   const uint64_t need = (sym_offsets[m] * b + 7) / 8;
   if (data_bytes < need || (need && !data)) return set_error(c, IG_EINVAL, "data too small");
+  if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
   hipStream_t s = c->stream;
   // chunks of the batch
   std::vector<Chunk> ch;

@@ -297,6 +297,8 @@ struct LaunchCfg {
   uint32_t grid_per_cu = 1;
   uint32_t set_cap = 8192;
   uint32_t filt_max_words = 16384;   // 64 KB of LDS
+  uint32_t map_log2 = 1;             // map slots >= kept << map_log2 (load <= 1/2)
+  uint32_t bloom_bits = 12;          // Bloom filter image: bits per retained key (within filt_max_words)
 };
 
 }  // namespace ig
@@ -312,7 +314,7 @@ struct ig_ctx {
   uint64_t held_bytes = 0;
 
   // corpus
-  ig::DevBuf data, offs, chunks_lpt, chunks_file, code, sym_of_code, qctr, status;
+  ig::DevBuf data, offs, chunks_lpt, chunks_file, code, sym_of_code, qctr, status, kdev;
   std::vector<uint64_t> h_offs;
   std::vector<uint32_t> file_chunk0;   // first chunk (file order) of each file, m+1 entries
   uint64_t m = 0, total_syms = 0, data_bytes = 0, nchunks = 0;
@@ -337,6 +339,7 @@ struct ig_ctx {
   // once-per-sequence counting: slab, per-chunk counts and histograms, bucketed records
   ig::DevBuf rec0, nrec, hist1, g1, scan_tmp, base1, bend, bshift, dscal, l1, l2, hist2, g2, fin, nsegs, seg0;
   uint64_t rec_cap = 0;         // records the bucketed arrays hold (multiple of the tile)
+  bool rec_floor = false;       // a caller set rec_cap: raise it only to the per-pass floor, not to the size guess
   ig::DevBuf sel_cid, sel_cnt, sel_klo, sel_khi, tie_a, tie_b, sort_tmp, hist, selstate, thist;
 
   ig_pass_stats last{};
@@ -381,6 +384,8 @@ int select_read(ig_ctx *c, uint64_t *kept, uint64_t *distinct);
 // map + filter over a table set (sizes bounded by k_max; the length is read on the device)
 int index_reserve(ig_ctx *c, TableSet &t, uint32_t n, uint64_t k_max);
 hipError_t index_enqueue(ig_ctx *c, TableSet &t, uint64_t k_max, const unsigned long long *kept_dev);
+// rebuild the current table's map and filter with the context's table shape (ig_table.hip)
+int reindex_current(ig_ctx *c);
 // featurize a device-resident batch into per-file rank bitmaps and CSR
 struct FeatBatch {
   const uint8_t *data;       // device

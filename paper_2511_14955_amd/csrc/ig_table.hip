@@ -82,7 +82,7 @@ __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const u
 // the kernels read the actual length from device memory.
 int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
   uint64_t cap = 1024;
-  while (cap < 2 * k_max) cap <<= 1;
+  while (cap < (k_max << c->lc.map_log2)) cap <<= 1;
   const uint32_t nbits = n * c->cfg.symbol_bits;
   const uint64_t maxw = c->lc.filt_max_words;
   uint32_t kind, words;
@@ -91,8 +91,8 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     words = (uint32_t)(((1ull << nbits) + 31) / 32);
   } else {
     kind = FILT_BLOOM;
-    uint64_t w = 64;   // about 12 bits per key, a power of two within [64, maxw]
-    while (w < (k_max * 12 + 31) / 32 && w < maxw) w <<= 1;
+    uint64_t w = 64;   // about bloom_bits bits per key, a power of two within [64, maxw]
+    while (w < (k_max * c->lc.bloom_bits + 31) / 32 && w < maxw) w <<= 1;
     words = (uint32_t)w;
   }
   uint32_t rb = 1;
@@ -369,6 +369,21 @@ hipError_t launch_col_counts(const uint32_t *bitmaps, uint64_t m, uint32_t words
   const uint32_t grid = (words + 255) / 256;
   hipLaunchKernelGGL(k_col_counts, dim3(grid), dim3(256), 0, s, bitmaps, m, words, kept, col_counts);
   return hipGetLastError();
+}
+
+// The current table indexed again (map, quotient map, filter image) with the context's table
+// shape; the table's keys and order are unchanged.
+int reindex_current(ig_ctx *c) {
+  if (c->fresh || !c->kept) return IG_OK;
+  TableSet &t = c->T();
+  int rc = index_reserve(c, t, t.n, t.kept);
+  if (rc) return rc;
+  const unsigned long long kept = t.kept;
+  hipStream_t s = c->stream;
+  hipError_t e = hipMemcpyAsync(c->kdev.p, &kept, sizeof kept, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = index_enqueue(c, t, t.kept, reinterpret_cast<const unsigned long long *>(c->kdev.p));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return check_hip(c, e, "re-index") ? IG_EDEVICE : IG_OK;
 }
 
 }  // namespace ig

@@ -43,11 +43,14 @@ static bool cache_lookup(const std::string &key, LaunchCfg *lc) {
   bool found = false;
   while (fgets(line, sizeof line, f)) {
     char k[600];
-    unsigned cs, bl, sc;
-    if (sscanf(line, "%599s %u %u %u", k, &cs, &bl, &sc) == 4 && key == k && shape_ok(cs, bl, sc)) {
+    unsigned cs, bl, sc, ml, fw;
+    if (sscanf(line, "%599s %u %u %u %u %u", k, &cs, &bl, &sc, &ml, &fw) == 6 && key == k && shape_ok(cs, bl, sc) &&
+        ml >= 1 && ml <= 3 && fw >= 1024 && fw <= 16384 && (fw & (fw - 1)) == 0) {
       lc->chunk_syms = cs;
       lc->block = bl;
       lc->set_cap = sc;
+      lc->map_log2 = ml;
+      lc->filt_max_words = fw;
       found = true;
     }
   }
@@ -60,7 +63,7 @@ static void cache_store(const std::string &key, const LaunchCfg &lc) {
   if (!path) return;
   FILE *f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %u %u %u\n", key.c_str(), lc.chunk_syms, lc.block, lc.set_cap);
+  fprintf(f, "%s %u %u %u %u %u\n", key.c_str(), lc.chunk_syms, lc.block, lc.set_cap, lc.map_log2, lc.filt_max_words);
   fclose(f);
 }
 
@@ -79,11 +82,17 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
       int rc = rebuild_chunks(c);
       if (rc) return rc;
     }
+    if (cached.map_log2 != start.map_log2 || cached.filt_max_words != start.filt_max_words) {
+      int rc = reindex_current(c);
+      if (rc) return rc;
+    }
     if (rep) {
       rep->n_candidates = 1;
       rep->cand[0].chunk_syms = cached.chunk_syms;
       rep->cand[0].block = cached.block;
       rep->cand[0].set_cap = cached.set_cap;
+      rep->cand[0].map_slots_log2 = cached.map_log2;
+      rep->cand[0].filter_max_words = cached.filt_max_words;
       rep->cand[0].pass_ms = -1.0;
       rep->best = 0;
       rep->identical = 1;
@@ -109,23 +118,30 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
   std::vector<uint64_t> ref_lo, ref_hi, ref_cnt;
   std::vector<ig_key> keys;
   std::vector<uint64_t> counts;
-  int best = -1, identical = 1;
+  int identical = 1;
   bool have_ref = false;
-  double best_ms = 1e30;
   uint32_t cur_chunk = c->lc.chunk_syms;
-  for (size_t i = 0; i < cands.size() && i < IG_TUNE_MAX; i++) {
-    c->lc = cands[i];
-    if (cands[i].chunk_syms != cur_chunk) {
+  uint32_t nrep = 0;
+  // Run pass n (twice, keeping the faster) with launch shape `lc` and compare its table with the
+  // first candidate's.  Returns the pass time, -1 when the shape does not fit the pass, or
+  // -2 - rc on another error.
+  auto trial = [&](const LaunchCfg &lc) -> double {
+    const bool retable = lc.map_log2 != c->lc.map_log2 || lc.filt_max_words != c->lc.filt_max_words;
+    c->lc = lc;
+    if (lc.chunk_syms != cur_chunk) {
       int rc = rebuild_chunks(c);
-      if (rc) return rc;
-      cur_chunk = cands[i].chunk_syms;
+      if (rc) return -2.0 + rc;
+      cur_chunk = lc.chunk_syms;
+    }
+    if (retable) {
+      int rc = reindex_current(c);
+      if (rc) return -2.0 + rc;
     }
     double ms = 1e30;
-    int ok = 1;
-    for (int rep_i = 0; rep_i < 2 && ok; rep_i++) {
+    for (int rep_i = 0; rep_i < 2; rep_i++) {
       int rc = ig_pass(c, n, k_keep);
-      if (rc == IG_EINVAL) { ok = 0; break; }   // launch shape does not fit this pass
-      if (rc) return rc;
+      if (rc == IG_EINVAL) return -1.0;   // launch shape does not fit this pass
+      if (rc) return -2.0 + rc;
       ms = std::min(ms, c->last.pass_ms);
       if (rep_i == 0) {
         const uint64_t kept = c->kept;
@@ -133,7 +149,7 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
         counts.resize(kept ? kept : 1);
         uint64_t got = 0;
         rc = ig_topk(c, kept, keys.data(), counts.data(), &got);
-        if (rc) return rc;
+        if (rc) return -2.0 + rc;
         if (!have_ref) {
           have_ref = true;
           for (uint64_t j = 0; j < got; j++) {
@@ -149,35 +165,74 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
         }
       }
       rc = ig_rewind(c);
-      if (rc) return rc;
+      if (rc) return -2.0 + rc;
     }
-    if (rep) {
-      rep->cand[i].chunk_syms = cands[i].chunk_syms;
-      rep->cand[i].block = cands[i].block;
-      rep->cand[i].set_cap = cands[i].set_cap;
-      rep->cand[i].pass_ms = ok ? ms : -1.0;
-      rep->n_candidates = (uint32_t)(i + 1);
-    }
-    if (!ok) continue;
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = (int)i;
-    }
-  }
-  if (best < 0) {
+    return ms;
+  };
+  auto record = [&](const LaunchCfg &lc, double ms) {
+    if (!rep || nrep >= IG_TUNE_MAX) { nrep++; return; }
+    rep->cand[nrep].chunk_syms = lc.chunk_syms;
+    rep->cand[nrep].block = lc.block;
+    rep->cand[nrep].set_cap = lc.set_cap;
+    rep->cand[nrep].map_slots_log2 = lc.map_log2;
+    rep->cand[nrep].filter_max_words = lc.filt_max_words;
+    rep->cand[nrep].pass_ms = ms;
+    rep->n_candidates = ++nrep;
+  };
+  auto restore = [&](int code, const char *msg) {
+    const LaunchCfg now = c->lc;
     c->lc = start;
     if (cur_chunk != start.chunk_syms) (void)rebuild_chunks(c);
-    return set_error(c, IG_EINVAL, "no launch shape fits this pass");
+    if (now.map_log2 != start.map_log2 || now.filt_max_words != start.filt_max_words) (void)reindex_current(c);
+    return msg ? set_error(c, code, "%s", msg) : code;
+  };
+  // stage 1: the launch shape, with the starting table sizes
+  int best = -1;
+  uint32_t win_idx = 0;   // the winner's entry in the report
+  double best_ms = 1e30;
+  for (size_t i = 0; i < cands.size(); i++) {
+    const double ms = trial(cands[i]);
+    if (ms <= -2.0) return restore((int)(ms + 2.0), nullptr);
+    record(cands[i], ms);
+    if (ms >= 0 && ms < best_ms) {
+      best_ms = ms;
+      best = (int)i;
+      win_idx = nrep - 1;
+    }
   }
-  c->lc = cands[best];
-  if (cur_chunk != cands[best].chunk_syms) {
-    int rc = rebuild_chunks(c);
-    if (rc) return rc;
+  if (best < 0) return restore(IG_EINVAL, "no launch shape fits this pass");
+  // stage 2: the table sizes (map load, filter image) with that launch shape
+  LaunchCfg win = cands[best];
+  for (uint32_t ml : {1u, 2u})
+    for (uint32_t fw : {8192u, 16384u}) {
+      LaunchCfg lc = cands[best];
+      lc.map_log2 = ml;
+      lc.filt_max_words = fw;
+      if (ml == start.map_log2 && fw == start.filt_max_words) continue;   // measured in stage 1
+      const double ms = trial(lc);
+      if (ms <= -2.0) return restore((int)(ms + 2.0), nullptr);
+      record(lc, ms);
+      if (ms >= 0 && ms < best_ms) {
+        best_ms = ms;
+        win = lc;
+        win_idx = nrep - 1;
+      }
+    }
+  // the winner's chunks and index
+  {
+    const LaunchCfg now = c->lc;
+    c->lc = win;
+    if (win.chunk_syms != cur_chunk) {
+      int rc = rebuild_chunks(c);
+      if (rc) return rc;
+    }
+    if (win.map_log2 != now.map_log2 || win.filt_max_words != now.filt_max_words) {
+      int rc = reindex_current(c);
+      if (rc) return rc;
+    }
   }
-  if (rep) {
-    rep->best = (uint32_t)best;
-    rep->identical = identical;
-  }
+  if (rep) rep->best = win_idx;
+  if (rep) rep->identical = identical;
   if (!identical) return set_error(c, IG_EDEVICE, "launch shapes gave different tables");
   cache_store(key, c->lc);
   return IG_OK;
@@ -201,4 +256,42 @@ extern "C" int ig_set_launch(ig_ctx *c, uint32_t chunk_syms, uint32_t block, uin
   c->lc.set_cap = set_cap;
   if (rechunk && c->loaded) return rebuild_chunks(c);
   return IG_OK;
+}
+
+static bool tables_ok(const ig_table_shape &t) {
+  return t.map_slots_log2 >= 1 && t.map_slots_log2 <= 3 && t.filter_bits_per_key >= 4 && t.filter_bits_per_key <= 32 &&
+         t.filter_max_words >= 1024 && t.filter_max_words <= 16384 && (t.filter_max_words & (t.filter_max_words - 1)) == 0 &&
+         (t.sparse_slots == 0 || (t.sparse_slots >= 1024 && t.sparse_slots <= (1ull << 31) &&
+                                  (t.sparse_slots & (t.sparse_slots - 1)) == 0));
+}
+
+extern "C" int ig_get_tables(const ig_ctx *c, ig_table_shape *t) {
+  if (!c || !t) return IG_EINVAL;
+  std::memset(t, 0, sizeof *t);
+  t->map_slots_log2 = c->lc.map_log2;
+  t->filter_bits_per_key = c->lc.bloom_bits;
+  t->filter_max_words = c->lc.filt_max_words;
+  t->sparse_slots = c->tkey_slots;
+  t->record_capacity = c->rec_cap;
+  return IG_OK;
+}
+
+extern "C" int ig_set_tables(ig_ctx *c, const ig_table_shape *t) {
+  if (!c || !t) return IG_EINVAL;
+  if (c->sticky) return set_error(c, IG_EDEVICE, "context has a sticky device error: %s", c->err.c_str());
+  if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
+  if (!tables_ok(*t)) return set_error(c, IG_EINVAL, "bad table shape");
+  if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
+  const bool reindex = t->map_slots_log2 != c->lc.map_log2 || t->filter_bits_per_key != c->lc.bloom_bits ||
+                       t->filter_max_words != c->lc.filt_max_words;
+  c->lc.map_log2 = t->map_slots_log2;
+  c->lc.bloom_bits = t->filter_bits_per_key;
+  c->lc.filt_max_words = t->filter_max_words;
+  if (t->sparse_slots) c->tkey_slots = t->sparse_slots;
+  if (t->record_capacity) {
+    const uint64_t T = dedup_tile();
+    c->rec_cap = (t->record_capacity + T - 1) / T * T;
+    c->rec_floor = true;
+  }
+  return reindex ? reindex_current(c) : IG_OK;
 }

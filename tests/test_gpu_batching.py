@@ -62,3 +62,70 @@ def test_autotune_is_deterministic_and_keeps_state():
     g.pass_(5, 20000)
     keys, counts = g.topk()
     assert np.array_equal(keys, exp[4][0]) and np.array_equal(counts, exp[4][1])
+    axes = {(c["map_slots_log2"], c["filter_max_words"]) for c in rep["candidates"]}
+    assert {(1, 8192), (2, 8192), (2, 16384), (1, 16384)} <= axes     # table sizes were searched too
+    tables = g.tables()
+    assert (tables["map_slots_log2"], tables["filter_max_words"]) == (rep["best"]["map_slots_log2"],
+                                                                      rep["best"]["filter_max_words"])
+
+
+@pytest.mark.parametrize("shape", [dict(map_slots_log2=3, filter_bits_per_key=4, filter_max_words=1024),
+                                   dict(map_slots_log2=2, filter_bits_per_key=32, filter_max_words=4096),
+                                   dict(map_slots_log2=1, filter_bits_per_key=20, filter_max_words=16384)])
+def test_table_shapes_same_result(shape):
+    """Map load and filter sizes change speed only; a change between passes re-indexes the current
+    table, so the next pass already filters with the new sizes."""
+    corpus = gen.workload(2, m=40)
+    ns = list(range(1, 7))
+    say("table shape", shape)
+    exp, _ = oracle_tables(corpus, ns, 20000)
+    g = ig.Intergrams()
+    g.set_tables(**shape)
+    got = gpu_tables(corpus, ns[:3], 20000, ctx=g)[0]
+    g.set_tables(map_slots_log2=1, filter_bits_per_key=12, filter_max_words=16384)   # mid-chain
+    for n in ns[3:5]:
+        g.pass_(n, 20000)
+        got.append(g.topk())
+    g.set_tables(**shape)
+    g.pass_(6, 20000)
+    got.append(g.topk())
+    assert_tables_equal(got, exp, "table shape %s" % shape)
+    g.close()
+
+
+def test_forced_table_overflows_replay():
+    """Starting capacities far too small: the sparse key table of a fresh large-n pass and the
+    Eq. 2 record arrays overflow, the pass is replayed with larger ones, and the tables are the
+    oracle's."""
+    corpus = gen.workload(2, m=8)
+    say("fresh n=5 pass with a 16K-slot key table")
+    exp, _ = oracle_tables(corpus, [5], 3000)
+    g = ig.Intergrams()
+    g.set_tables(sparse_slots=1 << 14)
+    got = gpu_tables(corpus, [5], 3000, ctx=g)[0]
+    assert_tables_equal(got, exp, "sparse overflow")
+    assert g.last_stats()["replays"] >= 1
+    assert g.tables()["sparse_slots"] > 1 << 14
+    g.close()
+    corpus = gen.workload(2, m=48)
+    ns = list(range(1, 6))
+    say("chain n=1..5 with the record capacity reset to its floor before passes 3 and 5")
+    exp, _ = oracle_tables(corpus, ns, 20000)
+    g = ig.Intergrams()
+    got = gpu_tables(corpus, ns[:2], 20000, ctx=g)[0]
+    replays = []
+    for n in ns[2:]:
+        if n != 4:
+            g.set_tables(record_capacity=1)
+        g.pass_(n, 20000)
+        replays.append(g.last_stats()["replays"])
+        got.append(g.topk())
+    assert_tables_equal(got, exp, "record overflow")
+    assert replays[0] >= 1 and replays[2] >= 1, replays
+    with pytest.raises(ig.IGError) as e:
+        g.set_tables(map_slots_log2=4)
+    assert e.value.code == ig.IG_EINVAL
+    with pytest.raises(ig.IGError) as e:
+        g.set_tables(sparse_slots=3000)
+    assert e.value.code == ig.IG_EINVAL
+    g.close()
