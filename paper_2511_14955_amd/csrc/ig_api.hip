@@ -363,8 +363,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     p.map = reinterpret_cast<const uint32_t *>(t.map.p);
     p.mmask = t.map_mask;
     p.rank_bits = t.rank_bits;
-    p.tkeys_lo = reinterpret_cast<const uint64_t *>(t.lo.p);
-    p.tkeys_hi = reinterpret_cast<const uint64_t *>(t.hi.p);
+    p.tkeys_lo = reinterpret_cast<const uint64_t *>(t.le_lo.p);   // stream forms, rank order
+    p.tkeys_hi = reinterpret_cast<const uint64_t *>(t.le_hi.p);
     if (t.has_qmap) {
       p.qmap = reinterpret_cast<const uint64_t *>(t.qmap.p);
       p.qflag = reinterpret_cast<const uint32_t *>(t.qflag.p);
@@ -380,6 +380,11 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // without LDS for the survivor rings the scan resolves survivors in place; so it does when
   // the previous table holds every (n-1)-gram over the alphabet (every window survives)
   if (p.qbytes && scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192) p.qbytes = 0;
+  if (p.qbytes) {
+    // the compacted scan's thread runs are whole stage words and at most 64 windows long
+    const uint64_t spd = 32 / b, span_max = c->lc.chunk_syms + 128 / b - 1;
+    if (spd * ((span_max + spd * c->lc.block - 1) / (spd * c->lc.block)) > 64) p.qbytes = 0;
+  }
   if (p.qbytes) {
     uint64_t space = 1;
     for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;

@@ -46,6 +46,46 @@ __host__ __device__ __forceinline__ uint64_t hash_key(uint64_t lo, uint64_t hi) 
   x *= 0xFF51AFD7ED558CCDull;
   return x ^ (x >> 29);
 }
+// Index keys.  The maps and filter images over a retained table are keyed by a gram's stream
+// form: its n symbols with the FIRST symbol in the LOWEST b bits (symbol r at bits [b r, b r + b)),
+// the order in which symbols sit in the little-endian bit stream that the scan stages (bytes as
+// stored; 2-bit symbols with the four of each byte reversed).  A window's stream form is then a
+// funnel shift of two staged words and its prefix a mask.  The retained table itself keeps the
+// canonical form (first symbol most significant, numeric order = lexicographic order).
+__host__ __device__ __forceinline__ uint64_t rev_pairs64(uint64_t x) {   // 2-bit digits of x in reverse order
+  x = ((x >> 2) & 0x3333333333333333ull) | ((x & 0x3333333333333333ull) << 2);
+  x = ((x >> 4) & 0x0F0F0F0F0F0F0F0Full) | ((x & 0x0F0F0F0F0F0F0F0Full) << 4);
+  return __builtin_bswap64(x);
+}
+__host__ __device__ __forceinline__ void stream_form(uint64_t lo, uint64_t hi, uint32_t n, uint32_t b, uint64_t *olo,
+                                                     uint64_t *ohi) {
+  const uint32_t nb = n * b;
+  if (nb == 0) { *olo = 0; *ohi = 0; return; }
+  if (nb <= 64) {
+    const uint64_t r = b == 8 ? __builtin_bswap64(lo) : rev_pairs64(lo);
+    *olo = r >> (64 - nb);
+    *ohi = 0;
+    return;
+  }
+  // 64 < nb <= 128: digit j of the canonical key (from the top) goes to digit j of the result
+  // (from the bottom)
+  const uint64_t dm = (1ull << b) - 1;
+  uint64_t rlo = 0, rhi = 0;
+  for (uint32_t j = 0; j < n; j++) {
+    const uint32_t src = nb - b * (j + 1);   // canonical position of digit j
+    const uint64_t d = (src >= 64 ? (hi >> (src - 64)) : (lo >> src) | (src ? (hi << (64 - src)) : 0ull)) & dm;
+    const uint32_t dst = b * j;
+    if (dst >= 64) rhi |= d << (dst - 64);
+    else rlo |= d << dst;
+  }
+  *olo = rlo;
+  *ohi = rhi;
+}
+// The stream form's low 32 bits folded with its high bits (a filter image's hash input).
+__host__ __device__ __forceinline__ uint32_t fold_le(uint64_t lo, uint64_t hi) {
+  const uint32_t a = (uint32_t)lo, c = (uint32_t)(lo >> 32);
+  return a ^ ((c >> 13) | (c << 19)) ^ (uint32_t)hi ^ (uint32_t)(hi >> 32) * 0x85EBCA6Bu;
+}
 // Quotient map over keys of w <= 64 bits.  qmix is a bijection of w-bit values (xor-shifts and
 // odd multiplies modulo 2^w); the top sbits of the mix choose the home slot and the low qbits are
 // stored in the slot, above the displacement from home (dbits) and rank+1 (rbits).  A slot's
@@ -62,14 +102,10 @@ __host__ __device__ __forceinline__ uint64_t qmix(uint64_t x, uint32_t w) {
   x = (x * 0xFF51AFD7ED558CCDull) & m;
   return x ^ (x >> s);
 }
-// Blocked Bloom filter position of a key (filter of `words` 32-bit words, a power of two): an
-// xor-shift, a fold to 32 bits and one 32 x 32 -> 64-bit multiply; the word and the three bits
-// come from the product's high word.  (The fold only adds collisions of about k / 2^32 per
-// query; a filter has no false negatives either way.)
-__host__ __device__ __forceinline__ uint32_t bloom_fold(uint64_t lo, uint64_t hi) {
-  const uint64_t x = lo ^ (lo >> 29) ^ hi ^ (hi >> 23);
-  return (uint32_t)x ^ (uint32_t)(x >> 32);
-}
+// Blocked Bloom filter position of a key's 32-bit fold (filter of `words` 32-bit words, a power
+// of two): one 32 x 32 -> 64-bit multiply; the word and the three bits come from the product's
+// high word.  (Folding only adds collisions of about k / 2^32 per query; a filter has no false
+// negatives either way.)
 __host__ __device__ __forceinline__ void bloom_pos(uint32_t v, uint32_t words, uint32_t *word, uint32_t *mask) {
   const uint32_t t = (uint32_t)(((uint64_t)v * 0x9E3779B1ull) >> 32);
   *word = t & (words - 1);
@@ -192,7 +228,7 @@ struct ScanParams {
   const uint32_t *map;
   uint64_t mmask;
   uint32_t rank_bits;            // low bits of a slot holding rank+1
-  const uint64_t *tkeys_lo, *tkeys_hi;   // previous table's keys, in rank order
+  const uint64_t *tkeys_lo, *tkeys_hi;   // previous table's keys (stream forms), in rank order
   const uint64_t *qmap;          // quotient map of the previous table (null: none)
   const uint32_t *qflag;         // non-zero: a key of that table did not fit its displacement field (lookups
                                  // then use the fingerprinted map and the table's keys)
@@ -282,6 +318,7 @@ struct DevBuf {
 // One retained table and its index (exact map key -> rank+1, compact filter image).
 struct TableSet {
   DevBuf lo, hi, cnt;
+  DevBuf le_lo, le_hi;            // the keys' stream forms, in rank order (probes confirm against them)
   DevBuf map, filt;               // map: 32-bit fingerprinted slots (rank+1 in the low rank_bits)
   DevBuf qmap, qflag;             // quotient map (keys of at most 64 bits) and its overflow flag
   uint64_t kept = 0, map_mask = 0;

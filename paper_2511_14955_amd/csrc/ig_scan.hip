@@ -32,6 +32,8 @@ template <> struct KeyT<1> {
   uint64_t lo;
   __device__ __forceinline__ void clear() { lo = 0; }
   template <int B> __device__ __forceinline__ void push(uint32_t s, uint64_t mlo, uint64_t) { lo = ((lo << B) | s) & mlo; }
+  // stream form: the new symbol enters at the top (bit `top` = (n-1) b), the first leaves at the bottom
+  template <int B> __device__ __forceinline__ void push_le(uint32_t s, uint32_t top) { lo = (lo >> B) | ((uint64_t)s << top); }
   template <int B> __device__ __forceinline__ uint64_t pre_lo() const { return lo >> B; }
   template <int B> __device__ __forceinline__ uint64_t pre_hi() const { return 0; }
   static constexpr uint64_t hi = 0;
@@ -42,6 +44,12 @@ template <> struct KeyT<2> {
   template <int B> __device__ __forceinline__ void push(uint32_t s, uint64_t, uint64_t mhi) {
     hi = ((hi << B) | (lo >> (64 - B))) & mhi;
     lo = (lo << B) | s;
+  }
+  template <int B> __device__ __forceinline__ void push_le(uint32_t s, uint32_t top) {
+    lo = (lo >> B) | (hi << (64 - B));
+    hi >>= B;
+    if (top >= 64) hi |= (uint64_t)s << (top - 64);
+    else lo |= (uint64_t)s << top;
   }
   template <int B> __device__ __forceinline__ uint64_t pre_lo() const { return (lo >> B) | (hi << (64 - B)); }
   template <int B> __device__ __forceinline__ uint64_t pre_hi() const { return hi >> B; }
@@ -259,19 +267,28 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         // survivor at each step: resolving survivors in place would run the probe on all 64
         // lanes for a few live ones.  Survivors' keys are compacted into the wavefront's
         // LDS ring instead (ballot + prefix count) and resolved 64 at a time, one per lane.
+        //
+        // Keys are stream forms (first symbol lowest): the stage is read one 32-bit word at a
+        // time, and the 64 bits that start at a window are a funnel shift of two neighbouring
+        // words (v_alignbit); the prefix is a mask of them, the last symbol a bit field.
         constexpr int RBC = 4;
+        constexpr uint32_t SPD = 32 / B;   // symbols per stage word
         uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
         uint16_t *qd = s_qd + (tid >> 6) * SCAN_QCAP;
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
+        const uint64_t rmask64 = rmask;
         uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
-        KeyT<1> k;
-        k.clear();
-        if (t_lo < t_hi)
-          for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, wbeg + t_lo + r, sbase), mlo, mhi);
+        const uint32_t pb = (n - 1) * B;   // prefix bits
+        const uint32_t pm_lo = pb >= 32 ? 0xFFFFFFFFu : ((1u << pb) - 1);
+        const uint32_t pm_hi = pb <= 32 ? 0u : (pb >= 64 ? 0xFFFFFFFFu : ((1u << (pb - 32)) - 1));
+        const uint64_t pmask = ((uint64_t)pm_hi << 32) | pm_lo;
         // Exact rank of each queued key's prefix.  With the quotient map one 8-byte slot read
         // decides (home and stored bits give back the key); otherwise the fingerprinted map and
         // the table's keys are probed.  An empty slot ends either probe.
         const bool useq = p.qmap != nullptr && *p.qflag == 0u;
+        const uint64_t dmax = (1ull << p.qs.dbits) - 1;
+        const uint32_t rsh = p.qs.rbits + p.qs.dbits;
+        const uint64_t qmaskq = p.qs.qbits ? ((1ull << p.qs.qbits) - 1) : 0ull;
         // Each dequeued key takes exactly one probe step (two neighbouring slots).  Slots that hold
         // other keys send the key back into the ring with the next displacement (a later drain
         // takes it), so a few displaced keys never hold up the other lanes of the wavefront.
@@ -283,38 +300,31 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           if (lane < cnt) {
             key = q[(head + lane) & (SCAN_QCAP - 1)];
             const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
-            const uint64_t plo = key >> B;
+            const uint64_t plo = key & pmask;
+            const uint32_t last = (uint32_t)(key >> pb) & ((1u << B) - 1);
+            const uint32_t code = s_code[last];
             uint32_t cid = LDS_EMPTY;   // not found
             if (useq) {
               // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
-              // slot 0); a key further out comes back with d+2
+              // slot 0); a key further out comes back with d+2.  A slot holds the key whose
+              // stored bits and displacement are exactly the wanted ones (rank+1 >= 1 below them).
               const uint64_t x = qmix(plo, p.qs.w);
               const uint64_t slot = ((x >> p.qs.qbits) + d) & p.mmask;
-              const uint64_t rem = p.qs.qbits ? (x & ((1ull << p.qs.qbits) - 1)) : 0ull;
               typedef unsigned long long u64x2_t __attribute__((ext_vector_type(2), aligned(8)));
               const u64x2_t e2 = *reinterpret_cast<const u64x2_t *>(p.qmap + slot);
-              const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
-              const uint64_t dmax = (1ull << p.qs.dbits) - 1;
-              const uint32_t rsh = p.qs.rbits + p.qs.dbits;
               const uint64_t e0 = e2.x, e1 = e2.y;
-              if (e0 != 0) {
-                if (((e0 >> p.qs.rbits) & dmax) == d && (e0 >> rsh) == rem) {
-                  cid = (((uint32_t)e0 & rmask) - 1) * p.sigma + code;
-                } else if (e1 != 0 && d + 1 <= dmax) {
-                  if (((e1 >> p.qs.rbits) & dmax) == d + 1 && (e1 >> rsh) == rem) {
-                    cid = (((uint32_t)e1 & rmask) - 1) * p.sigma + code;
-                  } else if (d + 2 <= dmax) {
-                    again = true;
-                    dnext = d + 2;
-                  }
-                }
-              }
+              const uint64_t want0 = ((x & qmaskq) << rsh) | ((uint64_t)d << p.qs.rbits);
+              const uint64_t want1 = want0 + (1ull << p.qs.rbits);
+              const bool m0 = (e0 & rmask64) != 0 && (e0 & ~rmask64) == want0;
+              const bool m1 = (e1 & rmask64) != 0 && (e1 & ~rmask64) == want1 && d + 1 <= dmax;
+              if (m0 || m1) cid = (((uint32_t)(m0 ? e0 : e1) & rmask) - 1) * p.sigma + code;
+              again = !(m0 || m1) && (e0 & rmask64) != 0 && (e1 & rmask64) != 0 && d + 2 <= dmax;
+              dnext = d + 2;
             } else {
               const uint64_t h = hash_key(plo, 0);
               const uint32_t fp = map_fp(h, p.rank_bits);
               uint64_t slot = h & p.mmask;
               uint32_t v = p.map[slot];
-              const uint32_t code = s_code[(uint32_t)(key & ((1u << B) - 1))];
               while (v != 0) {
                 if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
                   const uint32_t r = (v & rmask) - 1;
@@ -340,69 +350,87 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           tail += (uint32_t)__popcll(m);
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         };
-        // Staged position (symbols from the stage's first byte) of the last symbol of this
-        // thread's first window, and of the chunk's last window.  A batch that starts past the
-        // chunk's last window reads at the clamp, at most RBC - 1 symbols into the stage's
-        // padding, and none of its windows passes.
-        const uint32_t g0 = (uint32_t)(wbeg + n - 1 - (B == 8 ? sbase : 4 * sbase)) + (uint32_t)t_lo;
-        const uint32_t gmax = (uint32_t)(wend + n - 2 - (B == 8 ? sbase : 4 * sbase));
-        const uint32_t nmine = t_hi > t_lo ? (uint32_t)(t_hi - t_lo) : 0u;
+        // Thread runs: stage symbol positions [p0, p0 + run) with run a multiple of SPD, so a run
+        // starts on a stage word.  The chunk's windows sit at positions [ofirst, ofirst + nwin);
+        // vbits marks the run's positions that are windows of this chunk (run <= 64, checked by
+        // the host before it picks this kernel).  Runs past the chunk read clamped stage words and
+        // keep no window.
+        const uint32_t ofirst = (uint32_t)(wbeg - (B == 8 ? sbase : 4 * sbase));
+        const uint32_t span = ofirst + (uint32_t)nwin;
+        const uint32_t run = SPD * ((span + SPD * bs - 1) / (SPD * bs));
+        const uint32_t p0 = tid * run;
+        const uint32_t vlo = ofirst > p0 ? (ofirst - p0 < run ? ofirst - p0 : run) : 0u;
+        const uint32_t vhi = span > p0 ? (span - p0 < run ? span - p0 : run) : 0u;
+        const uint64_t vbits = vhi > vlo ? ((vhi >= 64 ? ~0ull : ((1ull << vhi) - 1)) & ~((1ull << vlo) - 1)) : 0ull;
+        const uint32_t vb_lo = (uint32_t)vbits, vb_hi = (uint32_t)(vbits >> 32);
+        const uint32_t *st32 = reinterpret_cast<const uint32_t *>(s_stage);
+        // a stage word with its symbols in stream order (2-bit: each byte's four reversed)
+        const uint32_t jcap = p.stage_bytes / 4 - 1;
+        auto rd = [&](uint32_t j) -> uint32_t {
+          uint32_t w = st32[j < jcap ? j : jcap];
+          if (B == 2) {
+            w = ((w >> 2) & 0x33333333u) | ((w & 0x33333333u) << 2);
+            w = ((w >> 4) & 0x0F0F0F0Fu) | ((w & 0x0F0F0F0Fu) << 4);
+          }
+          return w;
+        };
         // one copy of the loop per filter kind, so that no window branches on it
         auto windows = [&](auto kind) {
           constexpr int FK = decltype(kind)::value;
-          for (uint32_t it = 0; it < per; it += RBC) {
-            // branch-free, so that the RBC staged-symbol reads and then the RBC filter reads are
-            // each issued together
-            const uint32_t gb = g0 + it < gmax ? g0 + it : gmax;
-            uint64_t kk[RBC];
-            uint32_t sym[RBC], widx[RBC], bm[RBC], w[RBC];
-            uint32_t pass = 0;
-#pragma unroll
-            for (int u = 0; u < RBC; u++) {
-              const uint32_t g = gb + u;
-              sym[u] = B == 8 ? (uint32_t)s_stage[g] : ((uint32_t)s_stage[g >> 2] >> (6 - 2 * (g & 3))) & 3u;
-            }
-#pragma unroll
-            for (int u = 0; u < RBC; u++) {
-              k.template push<B>(sym[u], mlo, mhi);
-              kk[u] = k.lo;
-              const uint64_t plo = k.lo >> B;
-              if constexpr (FK == FILT_BLOOM) {
-                bloom_pos(bloom_fold(plo, 0), p.filt_words, &widx[u], &bm[u]);
-              } else if constexpr (FK == FILT_DIRECT) {
-                widx[u] = (uint32_t)(plo >> 5) & fmask;
-                bm[u] = 1u << (plo & 31);
-              }
-            }
-            if constexpr (FK != FILT_NONE) {
-#pragma unroll
-              for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
-#pragma unroll
-              for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
-            } else {
-              pass = (1u << RBC) - 1;
-            }
-            // the windows of this batch that are this thread's
-            pass &= nmine > it ? (nmine - it >= (uint32_t)RBC ? (1u << RBC) - 1 : (1u << (nmine - it)) - 1) : 0u;
-            // a rolled loop (the keys shift down one register per step) keeps a single copy of
-            // the drain in the loop body
+          uint32_t j = p0 / SPD;
+          uint32_t D0 = rd(j), D1 = rd(j + 1);
+          for (uint32_t it = 0; it < run; it += SPD, j++) {
+            const uint32_t D2 = rd(j + 2);
 #pragma unroll 1
-            for (int u = 0; u < RBC; u++) {
-              const bool sv = pass & 1u;
-              const uint64_t m = __ballot(sv);
-              if (sv) {
-                const uint32_t below =
-                    __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
-                q[at] = kk[0];
-                qd[at] = 0;
-              }
-              tail += (uint32_t)__popcll(m);
-              while (tail - head >= 64) drain(64);
-              pass >>= 1;
+            for (uint32_t e0 = 0; e0 < SPD; e0 += RBC) {
+              // the RBC windows at run positions it + e0 + u: keys, filter positions, then the
+              // RBC filter reads issued together
+              uint32_t widx[RBC], bm[RBC], w[RBC];
+              uint32_t pass = 0;
 #pragma unroll
-              for (int j = 0; j + 1 < RBC; j++) kk[j] = kk[j + 1];
+              for (int u = 0; u < RBC; u++) {
+                const uint32_t sh = B * (e0 + u);
+                const uint32_t pl = __builtin_amdgcn_alignbit(D1, D0, sh) & pm_lo;
+                const uint32_t ph = __builtin_amdgcn_alignbit(D2, D1, sh) & pm_hi;
+                if constexpr (FK == FILT_BLOOM) {
+                  bloom_pos(pl ^ ((ph >> 13) | (ph << 19)), p.filt_words, &widx[u], &bm[u]);
+                } else if constexpr (FK == FILT_DIRECT) {
+                  widx[u] = (pl >> 5) & fmask;
+                  bm[u] = 1u << (pl & 31);
+                }
+              }
+              if constexpr (FK != FILT_NONE) {
+#pragma unroll
+                for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
+#pragma unroll
+                for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
+              } else {
+                pass = (1u << RBC) - 1;
+              }
+              // the windows of this batch that belong to the chunk
+              const uint32_t rel = it + e0;
+              pass &= (rel & 32u ? vb_hi : vb_lo) >> (rel & 31u);
+              // a rolled loop keeps a single copy of the drain in the loop body; the survivor's
+              // 64 key bits are shifted out of the stage words again
+#pragma unroll 1
+              for (uint32_t u = 0; u < (uint32_t)RBC; u++) {
+                const bool sv = pass & 1u;
+                const uint64_t m = __ballot(sv);
+                if (sv) {
+                  const uint32_t below =
+                      __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                  const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
+                  const uint32_t sh = B * (e0 + u);
+                  q[at] = ((uint64_t)__builtin_amdgcn_alignbit(D2, D1, sh) << 32) | __builtin_amdgcn_alignbit(D1, D0, sh);
+                  qd[at] = 0;
+                }
+                tail += (uint32_t)__popcll(m);
+                while (tail - head >= 64) drain(64);
+                pass >>= 1;
+              }
             }
+            D0 = D1;
+            D1 = D2;
           }
         };
         if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
@@ -413,8 +441,17 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         KeyT<KW> k;
         k.clear();
         const uint64_t g0 = wbeg + t_lo;   // absolute symbol of the first window
-        for (uint32_t r = 0; r + 1 < n; r++) k.template push<B>(stage_sym<B>(s_stage, g0 + r, sbase), mlo, mhi);
+        // filtered passes look prefixes up by their stream form (first symbol lowest); the
+        // unfiltered ones count canonical keys
+        const uint32_t top = (n - 1) * B;
+        for (uint32_t r = 0; r + 1 < n; r++) {
+          const uint32_t sym = stage_sym<B>(s_stage, g0 + r, sbase);
+          if (MODE == MODE_FILTERED) k.template push_le<B>(sym, top);
+          else k.template push<B>(sym, mlo, mhi);
+        }
         if (MODE == MODE_FILTERED) {
+          const uint64_t pmlo = top >= 64 ? ~0ull : ((1ull << top) - 1);
+          const uint64_t pmhi = top <= 64 ? 0ull : (top >= 128 ? ~0ull : ((1ull << (top - 64)) - 1));
           // Windows are taken RB at a time: every window's key is rolled and filtered and the
           // first map slot of each survivor is read; then the keys of fingerprint matches are
           // read from the table; then the probes are resolved.  Up to RB independent reads
@@ -430,14 +467,15 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
             for (int u = 0; u < RB; u++) {
               if (t0 + u >= t_hi) continue;
               const uint64_t g = wbeg + t0 + u;
-              k.template push<B>(stage_sym<B>(s_stage, g + n - 1, sbase), mlo, mhi);
-              const uint64_t plo = k.template pre_lo<B>(), phi = k.template pre_hi<B>();
+              const uint32_t sym = stage_sym<B>(s_stage, g + n - 1, sbase);
+              k.template push_le<B>(sym, top);
+              const uint64_t plo = k.lo & pmlo, phi = k.hi & pmhi;
               uint64_t h = 0;
               if (p.filt_kind == FILT_DIRECT) {
                 if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
               } else if (p.filt_kind == FILT_BLOOM) {
                 uint32_t wi, bm;
-                bloom_pos(bloom_fold(plo, phi), p.filt_words, &wi, &bm);
+                bloom_pos(fold_le(plo, phi), p.filt_words, &wi, &bm);
                 const uint32_t w = s_filt[wi];
                 if ((w & bm) != bm) continue;
               }
@@ -448,7 +486,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               q_fp[u] = map_fp(h, p.rank_bits);
               q_lo[u] = plo;
               q_hi[u] = phi;
-              q_code[u] = s_code[(uint32_t)(k.lo & ((1u << B) - 1))];
+              q_code[u] = s_code[sym];
               live |= 1u << u;
             }
 #pragma unroll

@@ -23,6 +23,18 @@
 
 namespace ig {
 
+// The retained keys' stream forms (the form every index below is keyed by).
+__global__ void k_le_keys(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t n,
+                          uint32_t b, uint64_t *llo, uint64_t *lhi) {
+  const uint64_t kept = *kept_p;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t a, c;
+    stream_form(tlo[i], thi[i], n, b, &a, &c);
+    llo[i] = a;
+    lhi[i] = c;
+  }
+}
+
 // Slot: rank+1 in the low rank_bits bits, a fingerprint of the key's hash above them.
 __global__ void k_map_insert(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *map,
                              uint64_t mmask, uint32_t rank_bits) {
@@ -72,7 +84,7 @@ __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const u
       atomicOr(filt + (lo >> 5), 1u << (lo & 31));
     } else {
       uint32_t w, bm;
-      bloom_pos(bloom_fold(lo, hi), words, &w, &bm);
+      bloom_pos(fold_le(lo, hi), words, &w, &bm);
       atomicOr(filt + w, bm);
     }
   }
@@ -97,7 +109,9 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
   }
   uint32_t rb = 1;
   while (rb < 32 && (1ull << rb) <= k_max) rb++;   // rank+1 <= k_max fits
-  if (dev_reserve(c, ts.map, cap * 4) || dev_reserve(c, ts.filt, (uint64_t)words * 4)) return IG_ENOMEM;
+  if (dev_reserve(c, ts.map, cap * 4) || dev_reserve(c, ts.filt, (uint64_t)words * 4) ||
+      dev_reserve(c, ts.le_lo, std::max<uint64_t>(k_max, 1) * 8) || dev_reserve(c, ts.le_hi, std::max<uint64_t>(k_max, 1) * 8))
+    return IG_ENOMEM;
   ts.has_qmap = false;
   if (nbits <= 64) {
     QMapShape qs{};
@@ -114,6 +128,7 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
       ts.has_qmap = true;
     }
   }
+  ts.n = n;   // (the stream forms are computed for this gram length)
   ts.map_mask = cap - 1;
   ts.rank_bits = rb;
   ts.filt_words = words;
@@ -129,12 +144,14 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
   uint64_t g = (k_max + 255) / 256;
   if (g > 4096) g = 4096;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
-                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.map.p),
-                     ts.map_mask, ts.rank_bits);
-  hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
-                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, reinterpret_cast<uint32_t *>(ts.filt.p),
-                     ts.filt_words, ts.filt_kind);
+  const uint64_t *llo = reinterpret_cast<const uint64_t *>(ts.le_lo.p), *lhi = reinterpret_cast<const uint64_t *>(ts.le_hi.p);
+  hipLaunchKernelGGL(k_le_keys, dim3((uint32_t)g), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
+                     reinterpret_cast<const uint64_t *>(ts.hi.p), kept_dev, ts.n, c->cfg.symbol_bits,
+                     reinterpret_cast<uint64_t *>(ts.le_lo.p), reinterpret_cast<uint64_t *>(ts.le_hi.p));
+  hipLaunchKernelGGL(k_map_insert, dim3((uint32_t)g), dim3(256), 0, s, llo, lhi, kept_dev,
+                     reinterpret_cast<uint32_t *>(ts.map.p), ts.map_mask, ts.rank_bits);
+  hipLaunchKernelGGL(k_filter_build, dim3((uint32_t)g), dim3(256), 0, s, llo, lhi, kept_dev,
+                     reinterpret_cast<uint32_t *>(ts.filt.p), ts.filt_words, ts.filt_kind);
   if (ts.has_qmap) {
     if ((e = hipGetLastError()) == hipSuccess) e = launch_fill_u64(reinterpret_cast<uint64_t *>(ts.qmap.p), ts.map_mask + 2, 0, s);
     if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.qflag.p), 1, 0, s);
@@ -144,8 +161,7 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
     for (uint64_t r1 = 256; r0 < k_max; r1 = r1 < (1ull << 14) ? r1 * 4 : k_max) {
       uint64_t gb = (r1 - r0 + 255) / 256;
       if (gb > 4096) gb = 4096;
-      hipLaunchKernelGGL(k_qmap_insert, dim3((uint32_t)gb), dim3(256), 0, s, reinterpret_cast<const uint64_t *>(ts.lo.p),
-                         kept_dev, r0, r1, reinterpret_cast<unsigned long long *>(ts.qmap.p),
+      hipLaunchKernelGGL(k_qmap_insert, dim3((uint32_t)gb), dim3(256), 0, s, llo, kept_dev, r0, r1, reinterpret_cast<unsigned long long *>(ts.qmap.p),
                          reinterpret_cast<uint32_t *>(ts.qflag.p), ts.map_mask, ts.qs);
       r0 = r1;
     }
@@ -180,9 +196,7 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
   uint32_t *s_bm = s_filt + p.filt_words;
-  const uint32_t tid = threadIdx.x, bs = blockDim.x, n = p.n, nb = n * B;
-  const uint64_t mlo = (KW == 1) ? (nb >= 64 ? ~0ull : ((1ull << nb) - 1)) : ~0ull;
-  const uint64_t mhi = (KW == 2) ? (nb >= 128 ? ~0ull : ((1ull << (nb - 64)) - 1)) : 0ull;
+  const uint32_t tid = threadIdx.x, bs = blockDim.x, n = p.n;
   for (uint32_t i = tid; i < p.filt_words; i += bs) s_filt[i] = p.filt[i];
   if (p.lds_bitmap)
     for (uint32_t i = tid; i < p.words; i += bs) s_bm[i] = 0;
@@ -211,12 +225,16 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
           if (B == 8) return s_stage[g - a0];
           return (s_stage[(g >> 2) - a0] >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
         };
+        // the window's stream form (first symbol lowest), the form the table's index is keyed by
+        const uint32_t top = (n - 1) * B;
         auto push = [&](uint32_t sv) {
           if (KW == 2) {
-            khi = ((khi << B) | (klo >> (64 - B))) & mhi;
-            klo = (klo << B) | sv;
+            klo = (klo >> B) | (khi << (64 - B));
+            khi >>= B;
+            if (top >= 64) khi |= (uint64_t)sv << (top - 64);
+            else klo |= (uint64_t)sv << top;
           } else {
-            klo = ((klo << B) | sv) & mlo;
+            klo = (klo >> B) | ((uint64_t)sv << top);
           }
         };
         for (uint32_t r = 0; r + 1 < n; r++) push(sym(wbeg + t_lo + r));
@@ -226,7 +244,7 @@ __global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
             if (!((s_filt[klo >> 5] >> (klo & 31)) & 1u)) continue;
           } else {
             uint32_t wi, bm;
-            bloom_pos(bloom_fold(klo, khi), p.filt_words, &wi, &bm);
+            bloom_pos(fold_le(klo, khi), p.filt_words, &wi, &bm);
             const uint32_t w = s_filt[wi];
             if ((w & bm) != bm) continue;
           }
@@ -275,8 +293,8 @@ hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s) {
   p.map = reinterpret_cast<const uint32_t *>(ts.map.p);
   p.mmask = ts.map_mask;
   p.rank_bits = ts.rank_bits;
-  p.tkeys_lo = reinterpret_cast<const uint64_t *>(ts.lo.p);
-  p.tkeys_hi = reinterpret_cast<const uint64_t *>(ts.hi.p);
+  p.tkeys_lo = reinterpret_cast<const uint64_t *>(ts.le_lo.p);   // stream forms, rank order
+  p.tkeys_hi = reinterpret_cast<const uint64_t *>(ts.le_hi.p);
   p.bitmaps = fb.bitmaps;
   p.words = fb.words;
   const uint32_t bits = c->cfg.symbol_bits;
