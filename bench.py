@@ -201,6 +201,82 @@ def serve_stream(g, ig, requests, budget, n_streams, max_batch):
                       "table = this pass's n=%d top-k" % g.table_info()[0]}
 
 
+CHAINS = {  # workload -> (symbol bits, last n, k_keep, count bits)
+    1: (8, 4, 1000, 32),
+    3: (8, 16, 1000000, 64),
+    4: (2, 31, 1000000, 64),
+}
+
+
+def config_chain(ig, workload, threads, reps=3, tune_at=None):
+    """Every pass of a workload's chain (n = 1..N, k_keep fixed, Eq. 2) on one GPU: the device
+    time of each pass (median of `reps` runs, rewinding between them; graph-captured), its input
+    rate and window rate.  tune_at: pass whose launch shape and table sizes the autotuner picks
+    first (the rest of the chain keeps them)."""
+    import gen
+    bits, nmax, k, cbits = CHAINS[workload]
+    t0 = time.time()
+    corpus = gen.workload(workload, nthreads=threads)
+    log("workload %d: %d sequences, %d bytes, generated in %.1fs" % (workload, corpus.m, corpus.nbytes, time.time() - t0))
+    g = ig.Intergrams(symbol_bits=bits, freq=ig.FREQ_DOC, count_bits=cbits)
+    g.load(corpus)
+    rows, tune = [], None
+    t_chain = time.time()
+    for n in range(1, nmax + 1):
+        if tune_at == n:
+            tune = g.autotune(n, k)
+            log("workload %d: autotune at pass %d: best %s" % (workload, n, tune["best"]))
+        ms, scan = [], []
+        for r in range(reps):
+            if r:
+                g.rewind()
+            g.pass_(n, k)
+            st = g.last_stats()
+            ms.append(st["pass_ms"])
+            scan.append(st["scan_ms"])
+        med = sorted(ms)[len(ms) // 2]
+        rows.append({"n": n, "pass_ms": round(med, 4), "scan_ms": round(sorted(scan)[len(scan) // 2], 4),
+                     "GB_per_s": round(corpus.nbytes / (med * 1e-3) / 1e9, 3),
+                     "windows_per_s": float("%.4g" % (st["windows"] / (med * 1e-3))),
+                     "kept": g.table_info()[1], "distinct": st["distinct"], "records": st["records"],
+                     "replays": st["replays"]})
+        log("workload %d pass %d: %s" % (workload, n, rows[-1]))
+    lc = g.launch()
+    g.close()
+    total = sum(r["pass_ms"] for r in rows)
+    return {"workload": workload, "sequences": corpus.m, "bytes": corpus.nbytes, "symbol_bits": bits,
+            "k_keep": k, "count_bits": cbits, "passes": rows, "chain_ms": round(total, 3),
+            "chain_GB_per_s_per_pass": round(corpus.nbytes * nmax / (total * 1e-3) / 1e9, 3),
+            "launch": lc, "autotune_best": tune["best"] if tune else None,
+            "timing": "device time of each pass (hipEvents), median of %d runs, graph-captured" % reps,
+            "wall_s": round(time.time() - t_chain, 1)}
+
+
+def serve_saturation(g, ig, files, budget, n_streams, max_batch):
+    """Closed loop: every request submitted at once (the queue holds them all), so the serving
+    loop is never idle; served bytes over the span from the first submit to the last result."""
+    import numpy as np
+    offs = [np.array([0, len(f)], np.uint64) for f in files]
+    g.serve_start(max_inflight_bytes=budget, n_streams=n_streams, max_batch=max_batch, queue_capacity=1 << 20)
+    t0 = g.serve_now()
+    for i, f in enumerate(files):
+        assert g.submit(ig.REQ_FEATURIZE, f, offs[i], tag=i, t_arrival=t0) == ig.IG_OK
+    got = 0
+    while got < len(files):
+        res = g.poll()
+        assert all(r["status"] == ig.IG_OK for r in res)
+        got += len(res)
+        if not res:
+            time.sleep(1e-4)
+    span = g.serve_now() - t0
+    st = g.serve_stats()
+    g.serve_stop()
+    nbytes = int(sum(len(f) for f in files))
+    return {"requests": len(files), "bytes": nbytes, "seconds": round(span, 4),
+            "GB_per_s": round(nbytes / span / 1e9, 4), "requests_per_s": round(len(files) / span, 1),
+            "launches": st["launches"], "peak_running": st["peak_running"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +298,10 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving HBM budget in bytes")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=64)
+    ap.add_argument("--configs", default="1,3,4",
+                    help="other workloads whose whole chain is timed pass by pass (comma list; '' to skip)")
+    ap.add_argument("--saturation-requests", type=int, default=20000,
+                    help="requests of the closed-loop serving saturation run (0: skip)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the Intergrams pass is measured on a single MI355X; "
@@ -314,6 +394,12 @@ def main():
     if a.serve_requests:
         serving = serve_stream(g, ig, a.serve_requests, a.serve_budget, a.serve_streams, a.serve_batch)
         log("serving: %s" % serving)
+        if a.saturation_requests:
+            rs = gen.RequestStream()
+            files = [rs.file(i) for i in range(a.saturation_requests)]
+            serving["saturation"] = serve_saturation(g, ig, files, a.serve_budget, a.serve_streams, a.serve_batch)
+            log("serving saturation: %s" % serving["saturation"])
+            del files
     if not a.no_per_file:
         gp = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags | ig.FLAG_PER_FILE)
         lc = g.launch()
@@ -336,6 +422,10 @@ def main():
                                     "kernel": "the library's streaming-read kernel (16-byte non-temporal loads)"}
     log("attainable HBM read: %s" % extra["hbm_read_attainable"])
     g.close()
+    configs = {}
+    for w in [int(x) for x in a.configs.split(",") if x.strip()]:
+        configs[str(w)] = config_chain(ig, w, threads, tune_at={3: 8, 4: 16}.get(w))
+    extra["configs"] = configs
     quality = None
     theory_rows = None
     if a.recall_files:
