@@ -193,10 +193,16 @@ int ig_create(const ig_config *cfg, ig_ctx **out) {
     return IG_EDEVICE;
   }
   if (dev_reserve(c, c->qctr, 64) || dev_reserve(c, c->status, 64) || dev_reserve(c, c->kdev, 64) ||
-      dev_reserve(c, c->code, 256) ||
+      dev_reserve(c, c->zero, 64) || dev_reserve(c, c->code, 256) ||
       dev_reserve(c, c->sym_of_code, 256)) {
     ig_destroy(c);
     return IG_ENOMEM;
+  }
+  // a word that stays zero: the featurizing scan's "stop early" status
+  if (launch_fill_u32(reinterpret_cast<uint32_t *>(c->zero.p), 16, 0, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    ig_destroy(c);
+    return IG_EDEVICE;
   }
   *out = c;
   return IG_OK;
@@ -211,11 +217,11 @@ void ig_destroy(ig_ctx *c) {
       if (x) (void)hipGraphExecDestroy(x);
   c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
-                    &c->status, &c->kdev, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
+                    &c->status, &c->kdev, &c->zero, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
-    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.map, &t.filt, &t.qmap, &t.qflag};
+    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.le_lo, &t.le_hi, &t.map, &t.filt, &t.qmap, &t.qflag};
     for (DevBuf *b : tb) dev_release(c, *b);
   }
   for (auto &e : c->ev)

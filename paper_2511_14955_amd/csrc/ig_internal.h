@@ -202,7 +202,13 @@ struct Chunk {
 };
 
 enum PassMode { MODE_DENSE = 0, MODE_FILTERED = 1, MODE_SPARSE = 2 };
-enum FilterKind { FILT_NONE = 0, FILT_DIRECT = 1, FILT_BLOOM = 2 };
+// FILT_GBLOOM: a Bloom filter image too large for LDS (more than about 131K retained keys), read
+// from global memory, where it stays in L2; the others are copied into LDS.
+enum FilterKind { FILT_NONE = 0, FILT_DIRECT = 1, FILT_BLOOM = 2, FILT_GBLOOM = 3 };
+// 32-bit words of a table's filter image that a workgroup copies into LDS
+__host__ __device__ __forceinline__ uint32_t filt_lds_words(uint32_t kind, uint32_t words) {
+  return (kind == FILT_DIRECT || kind == FILT_BLOOM) ? words : 0u;
+}
 enum StatusBits { ST_TABLE_OVF = 2u, ST_REC_OVF = 4u };
 
 static constexpr uint32_t LDS_EMPTY = 0xFFFFFFFFu;
@@ -216,7 +222,7 @@ struct ScanParams {
   uint32_t nchunks;              // chunks of this launch
   uint32_t chunk_base;           // non-persistent launches: first chunk index
   uint32_t *qctr;                // persistent launches: work-queue counter
-  uint32_t persistent;
+  uint32_t persistent;           // 0: one chunk per workgroup, 1: work queue (qctr), 2: strided by the grid
   uint32_t n;                    // gram length
   uint32_t sigma;                // compacted alphabet size
   const uint8_t *code;           // symbol -> code (256 entries)
@@ -251,6 +257,10 @@ struct ScanParams {
   uint32_t set_cap;              // LDS de-duplication set entries (power of two)
   uint32_t stage_bytes;          // LDS staging bytes
   uint32_t qbytes;               // LDS bytes of the per-wavefront survivor rings (keys + displacements)
+  // featurize form: per-sequence rank bitmaps of fwords 32-bit words; lds_bitmap: a chunk
+  // collects its bits in LDS first
+  uint32_t *bitmaps;
+  uint32_t fwords, lds_bitmap;
 };
 
 // Once-per-sequence counting from chunk records (see ig_dedup.hip).
@@ -351,7 +361,7 @@ struct ig_ctx {
   uint64_t held_bytes = 0;
 
   // corpus
-  ig::DevBuf data, offs, chunks_lpt, chunks_file, code, sym_of_code, qctr, status, kdev;
+  ig::DevBuf data, offs, chunks_lpt, chunks_file, code, sym_of_code, qctr, status, kdev, zero;
   std::vector<uint64_t> h_offs;
   std::vector<uint32_t> file_chunk0;   // first chunk (file order) of each file, m+1 entries
   uint64_t m = 0, total_syms = 0, data_bytes = 0, nchunks = 0;
@@ -412,7 +422,8 @@ hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ,
                        uint32_t grid, uint32_t block, hipStream_t s);
 // set the kernel's LDS limit outside of any stream capture
 hipError_t prepare_scan(int bits, int kw, int mode, int occ, int count64);
-size_t scan_lds_bytes(const ScanParams &p, int mode, int occ);
+size_t scan_lds_bytes(const ScanParams &p, int mode, int occ, int feat = 0);
+hipError_t launch_scan_feat(const ScanParams &p, int bits, int kw, uint32_t grid, uint32_t block, hipStream_t s);
 // selection: reserve scratch, enqueue kernels (no host sync), read the kept length afterwards
 int select_reserve(ig_ctx *c, uint64_t nc, uint64_t k_keep);
 hipError_t select_enqueue(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits);

@@ -111,16 +111,22 @@ __device__ __forceinline__ uint32_t stage_sym(const uint8_t *s_stage, uint64_t g
   return (byte >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
 }
 
-// CMP: filter survivors are compacted into per-wavefront rings (filtered 64-bit keys only)
-template <int B, int KW, int MODE, int OCC, typename CT, int CMP>
+// CMP: filter survivors are compacted into per-wavefront rings (filtered 64-bit keys only).
+// FEAT: featurize instead of count (Figure 1's Boolean rows): the whole window is looked up in
+// the current table (n-grams), and a hit sets bit rank(window) of its sequence's bitmap (in LDS
+// for the chunk when it fits, else straight in HBM).  Filtered mode, Eq. 2 layout, no counts.
+template <int B, int KW, int MODE, int OCC, typename CT, int CMP, int FEAT>
 __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
   // the filter image is padded to 16 bytes, so that the 8-byte ring entries below stay aligned
-  uint32_t *s_set = s_filt + (MODE == MODE_FILTERED ? ((p.filt_words + 3u) & ~3u) : 0);
-  uint32_t *s_cnt = s_set + p.set_cap;                 // OCC only
+  const uint32_t filt_lds = MODE == MODE_FILTERED ? filt_lds_words(p.filt_kind, p.filt_words) : 0u;
+  uint32_t *s_set = s_filt + ((filt_lds + 3u) & ~3u);
+  uint32_t *s_bm = s_set;                              // FEAT: the chunk's rank bitmap, in place of the set
+  const uint32_t bm_lds = FEAT && p.lds_bitmap ? (p.fwords + 3u) & ~3u : 0u;
+  uint32_t *s_cnt = s_set + (FEAT ? bm_lds : p.set_cap);   // OCC only
   uint8_t *s_code = reinterpret_cast<uint8_t *>(s_cnt + (OCC ? p.set_cap : 0));
   // Eq. 2: histogram of this chunk's records over the level-1 buckets, one copy per
   // wavefront (a few hot buckets take most records; a shared copy would serialize them)
@@ -142,10 +148,14 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   const uint32_t fmask = p.filt_words - 1;
 
   if (MODE == MODE_FILTERED)
-    for (uint32_t i = tid; i < p.filt_words; i += bs) s_filt[i] = p.filt[i];
-  for (uint32_t i = tid; i < p.set_cap; i += bs) {
-    s_set[i] = LDS_EMPTY;
-    if (OCC) s_cnt[i] = 0;
+    for (uint32_t i = tid; i < filt_lds; i += bs) s_filt[i] = p.filt[i];
+  if (FEAT) {
+    for (uint32_t i = tid; i < bm_lds; i += bs) s_bm[i] = 0;
+  } else {
+    for (uint32_t i = tid; i < p.set_cap; i += bs) {
+      s_set[i] = LDS_EMPTY;
+      if (OCC) s_cnt[i] = 0;
+    }
   }
   for (uint32_t i = tid; i < 256; i += bs) s_code[i] = p.code[i];
   for (uint32_t i = tid; i < p.hist_words; i += bs) s_h1w[i] = 0;
@@ -205,7 +215,10 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   u32x4_t pf[PF ? PF : 1];
   if (tid == 0) {
     uint32_t c0 = END, c1 = END;
-    if (p.persistent) {
+    if (p.persistent == 2) {   // strided: chunks blockIdx.x, + gridDim.x, ...
+      c0 = blockIdx.x;
+      if (PF) c1 = blockIdx.x + gridDim.x;
+    } else if (p.persistent) {
       c0 = atomicAdd(p.qctr, 1u);
       if (PF) c1 = atomicAdd(p.qctr, 1u);
     } else {
@@ -225,7 +238,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
     const uint32_t cn = __builtin_amdgcn_readfirstlane(s_next);
     if (!valid_chunk(ci)) break;
     uint32_t claim = END;   // thread 0: the chunk after cn
-    if (PF && tid == 0 && valid_chunk(cn)) claim = atomicAdd(p.qctr, 1u);
+    if (PF && tid == 0 && valid_chunk(cn)) claim = p.persistent == 2 ? cn + gridDim.x : atomicAdd(p.qctr, 1u);
     const Span cur = have_nx ? nx : span_of(ci);
     const Chunk c = cur.c;
     const uint64_t wbeg = cur.wbeg, wend = cur.wend;
@@ -251,8 +264,15 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       const uint64_t t_lo = (uint64_t)tid * per;
       const uint64_t t_hi = t_lo + per < nwin ? t_lo + per : nwin;
       const uint64_t sbase = a0;
-      // one surviving candidate: de-duplicate in the chunk's LDS set
+      uint32_t *gbm = FEAT ? p.bitmaps + (uint64_t)c.file * p.fwords : nullptr;
+      // one surviving candidate: de-duplicate in the chunk's LDS set (FEAT: cid is the rank, whose
+      // bit is set in the sequence's bitmap)
       auto handle = [&](uint32_t cid) {
+        if constexpr (FEAT) {
+          if (p.lds_bitmap) atomicOr(s_bm + (cid >> 5), 1u << (cid & 31));
+          else atomicOr(gbm + (cid >> 5), 1u << (cid & 31));
+          return;
+        }
         uint32_t slot;
         const int ins = lds_insert(s_set, capmask, capshift, cid, &slot);
         if (OCC) {
@@ -278,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
         const uint64_t rmask64 = rmask;
         uint32_t head = 0, tail = 0;   // ring positions, the same in every lane of the wavefront
-        const uint32_t pb = (n - 1) * B;   // prefix bits
+        const uint32_t pb = (FEAT ? n : n - 1) * B;   // bits looked up: the prefix (FEAT: the whole window)
         const uint32_t pm_lo = pb >= 32 ? 0xFFFFFFFFu : ((1u << pb) - 1);
         const uint32_t pm_hi = pb <= 32 ? 0u : (pb >= 64 ? 0xFFFFFFFFu : ((1u << (pb - 32)) - 1));
         const uint64_t pmask = ((uint64_t)pm_hi << 32) | pm_lo;
@@ -301,8 +321,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
             key = q[(head + lane) & (SCAN_QCAP - 1)];
             const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
             const uint64_t plo = key & pmask;
-            const uint32_t last = (uint32_t)(key >> pb) & ((1u << B) - 1);
-            const uint32_t code = s_code[last];
+            const uint32_t code = FEAT ? 0u : s_code[(uint32_t)(key >> pb) & ((1u << B) - 1)];
             uint32_t cid = LDS_EMPTY;   // not found
             if (useq) {
               // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
@@ -392,7 +411,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
                 const uint32_t sh = B * (e0 + u);
                 const uint32_t pl = __builtin_amdgcn_alignbit(D1, D0, sh) & pm_lo;
                 const uint32_t ph = __builtin_amdgcn_alignbit(D2, D1, sh) & pm_hi;
-                if constexpr (FK == FILT_BLOOM) {
+                if constexpr (FK == FILT_BLOOM || FK == FILT_GBLOOM) {
                   bloom_pos(pl ^ ((ph >> 13) | (ph << 19)), p.filt_words, &widx[u], &bm[u]);
                 } else if constexpr (FK == FILT_DIRECT) {
                   widx[u] = (pl >> 5) & fmask;
@@ -401,7 +420,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               }
               if constexpr (FK != FILT_NONE) {
 #pragma unroll
-                for (int u = 0; u < RBC; u++) w[u] = s_filt[widx[u]];
+                for (int u = 0; u < RBC; u++) w[u] = FK == FILT_GBLOOM ? p.filt[widx[u]] : s_filt[widx[u]];
 #pragma unroll
                 for (int u = 0; u < RBC; u++) pass |= (uint32_t)((w[u] & bm[u]) == bm[u]) << u;
               } else {
@@ -434,6 +453,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           }
         };
         if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
+        else if (p.filt_kind == FILT_GBLOOM) windows(std::integral_constant<int, FILT_GBLOOM>{});
         else if (p.filt_kind == FILT_DIRECT) windows(std::integral_constant<int, FILT_DIRECT>{});
         else windows(std::integral_constant<int, FILT_NONE>{});
         while (tail != head) drain(tail - head < 64 ? tail - head : 64u);
@@ -450,8 +470,9 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           else k.template push<B>(sym, mlo, mhi);
         }
         if (MODE == MODE_FILTERED) {
-          const uint64_t pmlo = top >= 64 ? ~0ull : ((1ull << top) - 1);
-          const uint64_t pmhi = top <= 64 ? 0ull : (top >= 128 ? ~0ull : ((1ull << (top - 64)) - 1));
+          const uint32_t lb = FEAT ? top + B : top;   // bits looked up (FEAT: the whole window)
+          const uint64_t pmlo = lb >= 64 ? ~0ull : ((1ull << lb) - 1);
+          const uint64_t pmhi = lb <= 64 ? 0ull : (lb >= 128 ? ~0ull : ((1ull << (lb - 64)) - 1));
           // Windows are taken RB at a time: every window's key is rolled and filtered and the
           // first map slot of each survivor is read; then the keys of fingerprint matches are
           // read from the table; then the probes are resolved.  Up to RB independent reads
@@ -473,10 +494,10 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               uint64_t h = 0;
               if (p.filt_kind == FILT_DIRECT) {
                 if (!((s_filt[(uint32_t)(plo >> 5) & fmask] >> (plo & 31)) & 1u)) continue;
-              } else if (p.filt_kind == FILT_BLOOM) {
+              } else if (p.filt_kind == FILT_BLOOM || p.filt_kind == FILT_GBLOOM) {
                 uint32_t wi, bm;
                 bloom_pos(fold_le(plo, phi), p.filt_words, &wi, &bm);
-                const uint32_t w = s_filt[wi];
+                const uint32_t w = p.filt_kind == FILT_GBLOOM ? p.filt[wi] : s_filt[wi];
                 if ((w & bm) != bm) continue;
               }
               h = hash_key(plo, phi);
@@ -486,7 +507,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               q_fp[u] = map_fp(h, p.rank_bits);
               q_lo[u] = plo;
               q_hi[u] = phi;
-              q_code[u] = s_code[sym];
+              q_code[u] = FEAT ? 0u : s_code[sym];
               live |= 1u << u;
             }
 #pragma unroll
@@ -551,8 +572,19 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         if (q * bs + tid < nx.nw) reinterpret_cast<u32x4_t *>(s_stage)[q * bs + tid] = pf[q];
       staged = nx.nw < PF * bs ? nx.nw : PF * bs;
     }
+    // FEAT: the chunk's bitmap words that are set go into the sequence's bitmap
+    if (FEAT) {
+      uint32_t *gbm = p.bitmaps + (uint64_t)c.file * p.fwords;
+      for (uint32_t i = tid; i < bm_lds; i += bs) {
+        const uint32_t v = s_bm[i];
+        if (v) {
+          atomicOr(gbm + i, v);
+          s_bm[i] = 0;
+        }
+      }
+    }
     // set_cap is a multiple of the block, so every lane of a wavefront runs the same iterations
-    for (uint32_t i = tid; i < p.set_cap; i += bs) {
+    for (uint32_t i = tid; !FEAT && i < p.set_cap; i += bs) {
       const uint32_t cid = s_set[i];
       const bool full = cid != LDS_EMPTY;
       if (OCC) {
@@ -577,7 +609,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       }
     }
     __syncthreads();
-    if (!OCC) {
+    if (!OCC && !FEAT) {
       if (tid == 0) {
         p.nrec[c.fci] = s_nrec;
         s_nrec = 0;
@@ -607,22 +639,23 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   }
 }
 
-size_t scan_lds_bytes(const ScanParams &p, int mode, int occ) {
+size_t scan_lds_bytes(const ScanParams &p, int mode, int occ, int feat) {
   size_t b = p.stage_bytes;
-  if (mode == MODE_FILTERED) b += (size_t)((p.filt_words + 3u) & ~3u) * 4;
-  b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
+  if (mode == MODE_FILTERED) b += (size_t)((filt_lds_words(p.filt_kind, p.filt_words) + 3u) & ~3u) * 4;
+  if (feat) b += p.lds_bitmap ? (size_t)((p.fwords + 3u) & ~3u) * 4 : 0;
+  else b += (size_t)p.set_cap * 4 * (occ ? 2 : 1);
   b += 256;
   b += p.qbytes;
   b += (size_t)p.hist_words * 4;
   return b;
 }
 
-template <int B, int KW, int MODE, int OCC, typename CT>
+template <int B, int KW, int MODE, int OCC, typename CT, int FEAT = 0>
 static hipError_t launch_t(const ScanParams &p, uint32_t grid, uint32_t block, hipStream_t s) {
-  const size_t lds = scan_lds_bytes(p, MODE, OCC);
+  const size_t lds = scan_lds_bytes(p, MODE, OCC, FEAT);
   constexpr int can_cmp = (MODE == MODE_FILTERED && KW == 1) ? 1 : 0;
-  auto fn0 = k_scan<B, KW, MODE, OCC, CT, 0>;
-  auto fn1 = k_scan<B, KW, MODE, OCC, CT, can_cmp>;
+  auto fn0 = k_scan<B, KW, MODE, OCC, CT, 0, FEAT>;
+  auto fn1 = k_scan<B, KW, MODE, OCC, CT, can_cmp, FEAT>;
   if (grid == 0) {   // preparation call: allow the whole LDS of a CU (never issued during a capture)
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn0), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024 - 4096);
@@ -640,6 +673,16 @@ static hipError_t launch_m(const ScanParams &p, int occ, int count64, uint32_t g
   if (!occ) return launch_t<B, KW, MODE, 0, uint32_t>(p, grid, block, s);
   if (!count64) return launch_t<B, KW, MODE, 1, uint32_t>(p, grid, block, s);
   return launch_t<B, KW, MODE, 1, unsigned long long>(p, grid, block, s);
+}
+
+// The featurizing form of the scan (FEAT): filtered mode against the current table.  grid = 0
+// prepares the kernels' LDS limit.
+hipError_t launch_scan_feat(const ScanParams &p, int bits, int kw, uint32_t grid, uint32_t block, hipStream_t s) {
+  if (bits == 8)
+    return kw == 1 ? launch_t<8, 1, MODE_FILTERED, 0, uint32_t, 1>(p, grid, block, s)
+                   : launch_t<8, 2, MODE_FILTERED, 0, uint32_t, 1>(p, grid, block, s);
+  return kw == 1 ? launch_t<2, 1, MODE_FILTERED, 0, uint32_t, 1>(p, grid, block, s)
+                 : launch_t<2, 2, MODE_FILTERED, 0, uint32_t, 1>(p, grid, block, s);
 }
 
 hipError_t launch_scan(const ScanParams &p, int bits, int kw, int mode, int occ, int count64, uint32_t grid,

@@ -19,6 +19,9 @@
 // (word-contiguous, so the atomics coalesce).  A sequence's row is then the set
 // bits of its bitmap in increasing order: de-duplicated and sorted by
 // construction.
+#include <cstring>
+#include <mutex>
+
 #include "ig_internal.h"
 
 namespace ig {
@@ -102,9 +105,13 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
     kind = FILT_DIRECT;
     words = (uint32_t)(((1ull << nbits) + 31) / 32);
   } else {
-    kind = FILT_BLOOM;
-    uint64_t w = 64;   // about bloom_bits bits per key, a power of two within [64, maxw]
-    while (w < (k_max * c->lc.bloom_bits + 31) / 32 && w < maxw) w <<= 1;
+    // about bloom_bits bits per key, a power of two of at least 64 words; in LDS while that cap
+    // still leaves 4 bits per key, else in global memory (L2) at the full size (up to 64 MB)
+    const uint64_t want = (k_max * c->lc.bloom_bits + 31) / 32;
+    kind = maxw * 32 >= k_max * 4 ? FILT_BLOOM : FILT_GBLOOM;
+    const uint64_t cap = kind == FILT_BLOOM ? maxw : (1ull << 24);
+    uint64_t w = 64;
+    while (w < want && w < cap) w <<= 1;
     words = (uint32_t)w;
   }
   uint32_t rb = 1;
@@ -172,153 +179,61 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
 }
 
 // ------------------------------------------------------------------ featurize
-struct FeatParams {
-  const uint8_t *data;
-  const uint64_t *offs;
-  const Chunk *chunks;
-  uint32_t nchunks;
-  uint32_t n;
-  const uint32_t *filt;
-  uint32_t filt_words, filt_kind;
-  const uint32_t *map;
-  uint64_t mmask;
-  uint32_t rank_bits;
-  const uint64_t *tkeys_lo, *tkeys_hi;
-  uint32_t *bitmaps;
-  uint32_t words;        // per-sequence bitmap words (ceil(kept / 32))
-  uint32_t lds_bitmap;   // the bitmap fits in LDS
-  uint32_t stage_bytes;
-};
-
-template <int B, int KW>
-__global__ void __launch_bounds__(512) k_featurize(FeatParams p) {
-  extern __shared__ __align__(16) uint8_t lds[];
-  uint8_t *s_stage = lds;
-  uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
-  uint32_t *s_bm = s_filt + p.filt_words;
-  const uint32_t tid = threadIdx.x, bs = blockDim.x, n = p.n;
-  for (uint32_t i = tid; i < p.filt_words; i += bs) s_filt[i] = p.filt[i];
-  if (p.lds_bitmap)
-    for (uint32_t i = tid; i < p.words; i += bs) s_bm[i] = 0;
-  __syncthreads();
-  for (uint32_t ci = blockIdx.x; ci < p.nchunks; ci += gridDim.x) {
-    const Chunk c = p.chunks[ci];
-    const uint64_t fend = p.offs[c.file + 1], flen = fend - p.offs[c.file];
-    uint32_t *gbm = p.bitmaps + (uint64_t)c.file * p.words;
-    const uint64_t wbeg = c.s0;
-    uint64_t wend = c.s0 + c.nsym;
-    if (flen < n) wend = wbeg;
-    else if (wend > fend - n + 1) wend = fend - n + 1;
-    if (wbeg < wend) {
-      const uint64_t nwin = wend - wbeg;
-      const uint64_t byte_lo = (B == 8) ? wbeg : (wbeg >> 2);
-      const uint64_t byte_hi = (B == 8) ? (wend + n - 1) : ((wend + n - 2) >> 2) + 1;
-      const uint64_t a0 = byte_lo & ~15ull, a1 = (byte_hi + 15) & ~15ull;
-      const uint4 *src = reinterpret_cast<const uint4 *>(p.data + a0);
-      for (uint64_t i = tid; i < (a1 - a0) / 16; i += bs) reinterpret_cast<uint4 *>(s_stage)[i] = src[i];
-      __syncthreads();
-      const uint32_t per = (uint32_t)((nwin + bs - 1) / bs) | 1u;   // odd: lanes in different LDS banks
-      const uint64_t t_lo = (uint64_t)tid * per, t_hi = t_lo + per < nwin ? t_lo + per : nwin;
-      if (t_lo < t_hi) {
-        uint64_t klo = 0, khi = 0;
-        auto sym = [&](uint64_t g) -> uint32_t {
-          if (B == 8) return s_stage[g - a0];
-          return (s_stage[(g >> 2) - a0] >> (6 - 2 * (uint32_t)(g & 3))) & 3u;
-        };
-        // the window's stream form (first symbol lowest), the form the table's index is keyed by
-        const uint32_t top = (n - 1) * B;
-        auto push = [&](uint32_t sv) {
-          if (KW == 2) {
-            klo = (klo >> B) | (khi << (64 - B));
-            khi >>= B;
-            if (top >= 64) khi |= (uint64_t)sv << (top - 64);
-            else klo |= (uint64_t)sv << top;
-          } else {
-            klo = (klo >> B) | ((uint64_t)sv << top);
-          }
-        };
-        for (uint32_t r = 0; r + 1 < n; r++) push(sym(wbeg + t_lo + r));
-        for (uint64_t t = t_lo; t < t_hi; t++) {
-          push(sym(wbeg + t + n - 1));
-          if (p.filt_kind == FILT_DIRECT) {
-            if (!((s_filt[klo >> 5] >> (klo & 31)) & 1u)) continue;
-          } else {
-            uint32_t wi, bm;
-            bloom_pos(fold_le(klo, khi), p.filt_words, &wi, &bm);
-            const uint32_t w = s_filt[wi];
-            if ((w & bm) != bm) continue;
-          }
-          const uint64_t h = hash_key(klo, khi);
-          uint64_t slot = h & p.mmask;
-          int64_t r = -1;
-          const uint32_t fp = map_fp(h, p.rank_bits);
-          const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
-          for (;;) {
-            const uint32_t v = p.map[slot];
-            if (!v) break;
-            if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
-              const uint32_t rr = (v & rmask) - 1;
-              if (p.tkeys_lo[rr] == klo && p.tkeys_hi[rr] == khi) { r = rr; break; }
-            }
-            slot = (slot + 1) & p.mmask;
-          }
-          if (r < 0) continue;
-          if (p.lds_bitmap) atomicOr(s_bm + (r >> 5), 1u << (r & 31));
-          else atomicOr(gbm + (r >> 5), 1u << (r & 31));
-        }
-      }
-      __syncthreads();
-      if (p.lds_bitmap) {
-        for (uint32_t i = tid; i < p.words; i += bs) {
-          const uint32_t v = s_bm[i];
-          if (v) { atomicOr(gbm + i, v); s_bm[i] = 0; }
-        }
-      }
-    }
-    __syncthreads();
-  }
-}
-
+// Figure 1's Boolean rows run on the scan kernel in its featurizing form: the same staging,
+// filter image, survivor rings and quotient-map probes as a pass, with the whole window looked
+// up in the current table and each hit setting bit rank(window) in its sequence's bitmap.
+// Workgroups take the batch's chunks strided by the grid.
 hipError_t launch_featurize(ig_ctx *c, const FeatBatch &fb, hipStream_t s) {
-  FeatParams p{};
+  if (!fb.nchunks || !fb.words) return hipSuccess;
+  const TableSet &ts = c->ts[c->cur];
+  const uint32_t b = c->cfg.symbol_bits;
+  ScanParams p;
+  std::memset(&p, 0, sizeof p);
   p.data = fb.data;
   p.offs = fb.offs;
   p.chunks = fb.chunks;
   p.nchunks = fb.nchunks;
-  const TableSet &ts = c->ts[c->cur];
+  p.persistent = 2;
   p.n = ts.n;
+  p.sigma = 1;   // a hit's id is its rank
+  p.code = reinterpret_cast<const uint8_t *>(c->code.p);
   p.filt = reinterpret_cast<const uint32_t *>(ts.filt.p);
   p.filt_words = ts.filt_words;
   p.filt_kind = ts.filt_kind;
   p.map = reinterpret_cast<const uint32_t *>(ts.map.p);
   p.mmask = ts.map_mask;
   p.rank_bits = ts.rank_bits;
-  p.tkeys_lo = reinterpret_cast<const uint64_t *>(ts.le_lo.p);   // stream forms, rank order
+  p.tkeys_lo = reinterpret_cast<const uint64_t *>(ts.le_lo.p);
   p.tkeys_hi = reinterpret_cast<const uint64_t *>(ts.le_hi.p);
-  p.bitmaps = fb.bitmaps;
-  p.words = fb.words;
-  const uint32_t bits = c->cfg.symbol_bits;
-  p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * bits / 8 + 64 + 32) & ~15ull);
-  const size_t base = p.stage_bytes + (size_t)p.filt_words * 4;
-  const size_t limit = 160 * 1024 - 512;
-  p.lds_bitmap = base + (size_t)p.words * 4 <= limit ? 1u : 0u;
-  const size_t lds = base + (p.lds_bitmap ? (size_t)p.words * 4 : 0);
-  if (!fb.nchunks) return hipSuccess;
-  uint32_t grid = fb.nchunks < (uint32_t)c->n_cu * 2 ? fb.nchunks : (uint32_t)c->n_cu * 2;
-  const bool kw2 = (uint64_t)p.n * bits > 64;
-  const void *fn;
-  if (bits == 8) fn = kw2 ? reinterpret_cast<const void *>(k_featurize<8, 2>) : reinterpret_cast<const void *>(k_featurize<8, 1>);
-  else fn = kw2 ? reinterpret_cast<const void *>(k_featurize<2, 2>) : reinterpret_cast<const void *>(k_featurize<2, 1>);
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (bits == 8) {
-    if (kw2) hipLaunchKernelGGL((k_featurize<8, 2>), dim3(grid), dim3(512), lds, s, p);
-    else hipLaunchKernelGGL((k_featurize<8, 1>), dim3(grid), dim3(512), lds, s, p);
-  } else {
-    if (kw2) hipLaunchKernelGGL((k_featurize<2, 2>), dim3(grid), dim3(512), lds, s, p);
-    else hipLaunchKernelGGL((k_featurize<2, 1>), dim3(grid), dim3(512), lds, s, p);
+  if (ts.has_qmap) {
+    p.qmap = reinterpret_cast<const uint64_t *>(ts.qmap.p);
+    p.qflag = reinterpret_cast<const uint32_t *>(ts.qflag.p);
+    p.qs = ts.qs;
   }
-  return hipGetLastError();
+  p.status = reinterpret_cast<uint32_t *>(c->zero.p);
+  p.set_cap = 1024;   // (no set in this form)
+  p.stage_bytes = (uint32_t)(((uint64_t)c->lc.chunk_syms * b / 8 + 64 + 32) & ~15ull);
+  p.bitmaps = fb.bitmaps;
+  p.fwords = fb.words;
+  const uint32_t block = 1024;
+  const int kw = (uint64_t)ts.n * b > 64 ? 2 : 1;
+  const size_t limit = 160 * 1024 - 8192;
+  // survivor rings when the window fits 64 bits and thread runs stay within 64 windows; then
+  // the chunk's LDS bitmap if there is room left
+  if (kw == 1) {
+    const uint64_t spd = 32 / b, span_max = c->lc.chunk_syms + 128 / b - 1;
+    if (spd * ((span_max + spd * block - 1) / (spd * block)) <= 64) p.qbytes = (block / 64) * SCAN_QCAP * 10u;
+  }
+  if (scan_lds_bytes(p, MODE_FILTERED, 0, 1) > limit) p.qbytes = 0;
+  p.lds_bitmap = 1;
+  if (scan_lds_bytes(p, MODE_FILTERED, 0, 1) > limit) p.lds_bitmap = 0;
+  if (scan_lds_bytes(p, MODE_FILTERED, 0, 1) > limit) return hipErrorInvalidValue;
+  static std::once_flag prepared[2][2];
+  hipError_t e = hipSuccess;
+  std::call_once(prepared[b == 8][kw - 1], [&]() { e = launch_scan_feat(p, (int)b, kw, 0, 0, nullptr); });
+  if (e != hipSuccess) return e;
+  const uint32_t grid = fb.nchunks < (uint32_t)c->n_cu ? fb.nchunks : (uint32_t)c->n_cu;
+  return launch_scan_feat(p, (int)b, kw, grid, block, s);
 }
 
 // one workgroup per row: popcount (count_only) or write the set-bit positions in order
