@@ -30,7 +30,7 @@ def scan_sources_digest():
     """SHA-256 over the scan kernel's sources, to tie counter records to the code they measured."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("ig_scan.hip", "ig_internal.h"):
+    for f in ("ig_scan.hip", "ig_internal.h", "ig_table.hip"):
         with open(os.path.join(ROOT, "paper_2511_14955_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -48,7 +48,7 @@ def profiled_record(n, launch):
         for block in re.findall(r"```json\n(.*?)\n```", text, flags=re.S):
             rec = json.loads(block)
             if (rec.get("kernel") == "k_scan" and rec.get("n") == n and rec.get("scan_sources_sha256") == dig
-                    and list(rec.get("launch", [])) == list(launch)):
+                    and list(rec.get("launch", [])) + list(rec.get("tables", [])) == list(launch)):
                 return rec, os.path.relpath(path, ROOT)
     return None, None
 
@@ -290,7 +290,8 @@ def main():
     ap.add_argument("--no-per-file", action="store_true", help="skip the one-launch-per-file comparison")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--no-tune", action="store_true", help="keep the built-in launch shape")
-    ap.add_argument("--launch", default=None, help="fixed scan launch shape CHUNK,BLOCK,SETCAP (no autotune)")
+    ap.add_argument("--launch", default=None, help="fixed scan launch shape CHUNK,BLOCK,SETCAP[,WG_PER_CU] (no autotune)")
+    ap.add_argument("--tables", default=None, help="with --launch: table sizes MAP_SLOTS_LOG2,FILTER_MAX_WORDS")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="BYTES",
                     help="only stream BYTES through a plain device copy kernel 5 times (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=100000, help="requests replayed from the stream (0: skip)")
@@ -337,6 +338,9 @@ def main():
         st = g.last_stats()
         log("pass %d: %.3f ms (scan %.3f ms, select %.3f ms), kept %d, distinct %d, records %d" % (
             j, st["pass_ms"], st["scan_ms"], st["select_ms"], g.table_info()[1], st["distinct"], st["records"]))
+    if a.tables:
+        ml, fw = [int(x) for x in a.tables.split(",")]
+        g.set_tables(map_slots_log2=ml, filter_max_words=fw)   # re-indexes the n-1 table
     tune = None
     if not a.no_tune and not a.launch:
         t_t = time.time()
@@ -369,16 +373,19 @@ def main():
         a.n, ms_per_step, sum(pass_ms) / len(pass_ms), scan_avg, value))
 
     extra = {"device_pass_ms": round(sum(pass_ms) / len(pass_ms), 4),
+             "tables": {k: v for k, v in g.tables().items() if k in ("map_slots_log2", "filter_bits_per_key",
+                                                                       "filter_max_words")},
              "device_pass_ms_median": round(sorted(pass_ms)[len(pass_ms) // 2], 4),
              "scan_ms": round(scan_avg, 4),
              "select_ms": round(st["select_ms"], 4), "windows": st["windows"], "distinct_counted": st["distinct"],
              "split_file_records": st["records"],
              "launch": {"chunk_syms": st["chunk_syms"], "block": st["block"], "grid": st["grid"],
-                        "set_cap": g.launch()["set_cap"]},
+                        "set_cap": g.launch()["set_cap"], "wg_per_cu": g.launch()["wg_per_cu"]},
              "graph_captured": not (a.flags & 1)}
     if tune:
         extra["autotune"] = {"identical_tables": tune["identical"],
-                             "candidates": [[c["chunk_syms"], c["block"], c["set_cap"], round(c["pass_ms"], 3)]
+                             "candidates": [[c["chunk_syms"], c["block"], c["set_cap"], c["wg_per_cu"],
+                                             c["map_slots_log2"], c["filter_max_words"], round(c["pass_ms"], 3)]
                                             for c in tune["candidates"]]}
     # Figure 1's m x k Boolean matrix of the whole loaded corpus against this pass's table
     # (device bitmaps, then CSR copied to the host)
@@ -403,7 +410,7 @@ def main():
     if not a.no_per_file:
         gp = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_DOC, flags=a.flags | ig.FLAG_PER_FILE)
         lc = g.launch()
-        gp.set_launch(lc["chunk_syms"], lc["block"], lc["set_cap"])
+        gp.set_launch(lc["chunk_syms"], lc["block"], lc["set_cap"], lc["wg_per_cu"])
         gp.load(corpus)
         for j in range(1, a.n):
             gp.pass_(j, a.k)
@@ -417,6 +424,7 @@ def main():
         log("per-file form: %.3f ms, same table: %s" % ((t2 - t1) * 1e3, same))
         gp.close()
     g_launch = g.launch()
+    g_tables = g.tables()
     # what a plain streaming read attains on this device, for comparison with the pass's rate
     extra["hbm_read_attainable"] = {"GB_per_s": round(g.measure_read_bw(4 << 30, 5), 1), "bytes": 4 << 30,
                                     "kernel": "the library's streaming-read kernel (16-byte non-temporal loads)"}
@@ -462,7 +470,8 @@ def main():
         "extra": extra,
     }
     lc = g_launch
-    rec, tsrc = profiled_record(a.n, [lc["chunk_syms"], lc["block"], lc["set_cap"]])
+    rec, tsrc = profiled_record(a.n, [lc["chunk_syms"], lc["block"], lc["set_cap"], lc["wg_per_cu"],
+                                      g_tables["map_slots_log2"], g_tables["filter_max_words"]])
     out["roofline"]["traffic"] = rec["traffic_bytes_per_launch"] if rec else None
     out["roofline"]["traffic_source"] = tsrc
     out["roofline"]["valu_issue"] = valu_issue(rec, scan_avg)

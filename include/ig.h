@@ -72,6 +72,15 @@ typedef struct {
   void    *stream;       /* hipStream_t to run on; NULL: the library creates one */
   uint64_t hbm_budget;   /* bytes of device memory this context may hold; 0 = no limit */
   uint32_t flags;        /* IG_FLAG_* */
+  /* Optional device allocator, e.g. a framework's caching allocator.  When alloc is set (free
+   * must be too), every device buffer the context holds is taken from alloc(bytes, stream,
+   * alloc_user) and given back through free(p, stream, alloc_user); alloc returns NULL on
+   * failure (the call then fails with IG_ENOMEM).  stream is the context's stream; a buffer is
+   * given back only after the work that used it has finished.  Both are called from the
+   * thread making the library call (and from the serving thread while serving). */
+  void *(*alloc)(size_t bytes, void *stream, void *user);
+  void  (*free)(void *p, void *stream, void *user);
+  void   *alloc_user;
 } ig_config;
 
 #define IG_FLAG_NO_GRAPH      1u  /* launch pass kernels directly instead of a captured hipGraph */
@@ -85,7 +94,9 @@ void ig_config_default(ig_config *cfg);
 int  ig_create(const ig_config *cfg, ig_ctx **out);
 void ig_destroy(ig_ctx *ctx);
 
-/* Load m sequences, replacing any previous corpus and resetting the pass chain.
+/* Load m sequences (the problem statement's m input sequences over an alphabet; an n-gram is n
+ * consecutive symbols of one sequence, so sequence boundaries are kept), replacing any previous
+ * corpus and resetting the pass chain.
  *  data:        symbol stream; symbol i occupies bits [i*b, i*b+b) of the stream,
  *               most significant first within each byte (bytes when b = 8).
  *  data_bytes:  size of data; must cover sym_offsets[m] symbols.
@@ -116,17 +127,20 @@ int  ig_pass(ig_ctx *ctx, uint32_t n, uint64_t k_keep);
  * ig_pass), then those of ig_pass; on an error the passes that completed remain. */
 int  ig_intergrams(ig_ctx *ctx, uint32_t n, uint64_t k, double z);
 
-/* Undo the last pass: the table retained before it becomes current again
+/* Undo the last pass (the chain of Algorithm 3's retained sets P^(j), one level back): the
+ * table retained before it becomes current again
  * (one level; the state right after ig_load_batch counts as a level), so the
  * last pass can be run again.  Device-side pointer swap, no copy.
  * IG_ESTATE if there is nothing to undo. */
 int  ig_rewind(ig_ctx *ctx);
 
-/* Copy the first min(k, kept) entries of the retained table (host buffers of k
- * entries; counts may be NULL).  *k_out = number copied.  IG_ESTATE before a pass. */
+/* The result of Algorithm 3's final k-argmax: copy the first min(k, kept) entries of the
+ * retained table, in the order (count desc, key asc) (host buffers of k entries; keys as above;
+ * counts may be NULL; counts are Eq. 1 or Eq. 2 frequencies by ig_config.freq).
+ * *k_out = number copied.  IG_ESTATE before a pass. */
 int  ig_topk(ig_ctx *ctx, uint64_t k, ig_key *keys, uint64_t *counts, uint64_t *k_out);
 
-/* Gram length n and size of the retained table (0, 0 before any pass). */
+/* Gram length n and size of the retained table P^(n) of Algorithm 3 (0, 0 before any pass). */
 int  ig_table_info(const ig_ctx *ctx, uint32_t *n, uint64_t *kept);
 
 /* Boolean feature rows (Figure 1) of m new sequences against the retained table:
@@ -197,15 +211,17 @@ const char *ig_last_error(const ig_ctx *ctx);
  * chunk_syms: symbols per work item (a chunk of one sequence plus its n-1
  * symbol halo, 1024..65536); block: threads per workgroup (256, 512, 1024);
  * set_cap: LDS de-duplication set entries (a power of two, 1024..32768, at
- * least block).  IG_EINVAL otherwise.  The shape changes speed only, never
- * results.
+ * least block); wg_per_cu: scan workgroups per compute unit (1 or 2; a pass
+ * whose workgroup LDS does not fit half a CU runs one per CU).
+ * IG_EINVAL otherwise.  The shape changes speed only, never results.
  *
  * ig_autotune runs pass n on the loaded corpus for each candidate shape
  * (rewinding after each), checks that all candidates return the same table,
  * and keeps the fastest; the chain state is left as it was.  It searches the
  * launch shape first, then, with the best one, the table sizes of
  * ig_set_tables (map_slots_log2 1 or 2, filter_max_words 8192 or 16384),
- * which apply to the current table's index.  With the
+ * which apply to the current table's index, and last two workgroups per CU
+ * (Bloom image in L2, 4096-entry LDS set, chunks of 12288 or 16384 symbols).  With the
  * environment variable IG_TUNE_CACHE naming a file, results are read from and
  * appended to it, keyed by device, corpus shape and (n, k_keep).
  * --------------------------------------------------------------------------- */
@@ -213,7 +229,7 @@ const char *ig_last_error(const ig_ctx *ctx);
 typedef struct {
   uint32_t n_candidates;
   struct {
-    uint32_t chunk_syms, block, set_cap, map_slots_log2, filter_max_words;
+    uint32_t chunk_syms, block, set_cap, wg_per_cu, map_slots_log2, filter_max_words;
     double pass_ms;             /* < 0: shape unusable for this pass */
   } cand[IG_TUNE_MAX];
   uint32_t best;
@@ -221,8 +237,9 @@ typedef struct {
   int      from_cache;
 } ig_tune_report;
 int ig_autotune(ig_ctx *ctx, uint32_t n, uint64_t k_keep, ig_tune_report *rep);
-int ig_get_launch(const ig_ctx *ctx, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap);
-int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set_cap);
+int ig_get_launch(const ig_ctx *ctx, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap,
+                  uint32_t *wg_per_cu);
+int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set_cap, uint32_t wg_per_cu);
 
 /* ---------------------------------------------------------------------------
  * Table sizes (speed only, never results).

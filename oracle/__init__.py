@@ -21,12 +21,13 @@ FREQ_DOC, FREQ_OCC = 0, 1
 OK, EINVAL, ESTATE, ENOMEM, ETRUNC = 0, -1, -2, -3, -4
 
 
-def build(force=False, out=None, defines=()):
-    """Compile the oracle with g++ (``defines`` is for planted-mistake tests)."""
+def build(force=False, out=None, defines=(), flags=()):
+    """Compile the oracle with g++ (``defines`` is for planted-mistake tests, ``flags`` for the
+    sanitizer build)."""
     so = out or _SO
     if force or not os.path.exists(so):
         tmp = so + ".tmp%d" % os.getpid()
-        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread"]
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread"] + list(flags)
         cmd += ["-D%s" % d for d in defines]
         cmd += [os.path.join(_HERE, "ig_oracle.cpp"), "-o", tmp]
         subprocess.check_call(cmd)

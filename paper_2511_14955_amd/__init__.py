@@ -15,7 +15,8 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libintergrams.so")
+# IG_LIBRARY may name another build of the library (the host-sanitized libintergrams_san.so)
+LIB_PATH = os.environ.get("IG_LIBRARY") or os.path.join(_HERE, "libintergrams.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "ig.h")
 
 IG_OK, IG_EINVAL, IG_ESTATE, IG_ENOMEM, IG_ETRUNC, IG_EOVERFLOW, IG_EDEVICE, IG_EBUSY = 0, -1, -2, -3, -4, -5, -6, -7
@@ -38,10 +39,15 @@ class ig_key(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64)]
 
 
+# optional device allocator hooks of ig_config
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class ig_config(ctypes.Structure):
     _fields_ = [("symbol_bits", ctypes.c_uint32), ("freq", ctypes.c_int), ("count_bits", ctypes.c_uint32),
                 ("device", ctypes.c_int), ("stream", ctypes.c_void_p), ("hbm_budget", ctypes.c_uint64),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class ig_pass_stats(ctypes.Structure):
@@ -53,7 +59,8 @@ class ig_pass_stats(ctypes.Structure):
 
 class _tune_cand(ctypes.Structure):
     _fields_ = [("chunk_syms", ctypes.c_uint32), ("block", ctypes.c_uint32), ("set_cap", ctypes.c_uint32),
-                ("map_slots_log2", ctypes.c_uint32), ("filter_max_words", ctypes.c_uint32), ("pass_ms", ctypes.c_double)]
+                ("wg_per_cu", ctypes.c_uint32), ("map_slots_log2", ctypes.c_uint32),
+                ("filter_max_words", ctypes.c_uint32), ("pass_ms", ctypes.c_double)]
 
 
 class ig_table_shape(ctypes.Structure):
@@ -125,8 +132,8 @@ def load_library(path=LIB_PATH):
     lib.ig_last_error.argtypes = [vp]
     lib.ig_last_error.restype = ctypes.c_char_p
     lib.ig_autotune.argtypes = [vp, u32, u64, P(ig_tune_report)]
-    lib.ig_get_launch.argtypes = [vp, P(u32), P(u32), P(u32)]
-    lib.ig_set_launch.argtypes = [vp, u32, u32, u32]
+    lib.ig_get_launch.argtypes = [vp, P(u32), P(u32), P(u32), P(u32)]
+    lib.ig_set_launch.argtypes = [vp, u32, u32, u32, u32]
     lib.ig_get_tables.argtypes = [vp, P(ig_table_shape)]
     lib.ig_set_tables.argtypes = [vp, P(ig_table_shape)]
     lib.ig_serve_start.argtypes = [vp, P(ig_serve_config)]
@@ -156,13 +163,21 @@ def _as_host(corpus_or_data, offsets=None):
 class Intergrams:
     """One library context on one GPU."""
 
-    def __init__(self, symbol_bits=8, freq=FREQ_DOC, count_bits=64, device=0, stream=None, hbm_budget=0, flags=0):
+    def __init__(self, symbol_bits=8, freq=FREQ_DOC, count_bits=64, device=0, stream=None, hbm_budget=0, flags=0,
+                 allocator=None):
+        """allocator: optional (alloc(bytes, stream) -> device pointer int or 0, free(pointer, stream))
+        pair of Python callables that then hold every device buffer of the context."""
         self._lib = load_library()
         cfg = ig_config()
         self._lib.ig_config_default(ctypes.byref(cfg))
         cfg.symbol_bits, cfg.freq, cfg.count_bits, cfg.device = symbol_bits, freq, count_bits, device
         cfg.stream = stream if stream is None or isinstance(stream, int) else int(stream.cuda_stream)
         cfg.hbm_budget, cfg.flags = hbm_budget, flags
+        self._hooks = None
+        if allocator is not None:
+            fa, ff = allocator
+            self._hooks = (ALLOC_FN(lambda n, st, u: fa(n, st) or None), FREE_FN(lambda p, st, u: ff(p, st)))
+            cfg.alloc, cfg.free = self._hooks
         h = ctypes.c_void_p()
         rc = self._lib.ig_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc:
@@ -273,19 +288,19 @@ class Intergrams:
         """Search the scan's launch shape on pass n (chain state unchanged); returns a report dict."""
         rep = ig_tune_report()
         self._check(self._lib.ig_autotune(self._h, n, k_keep, ctypes.byref(rep)))
-        cands = [{"chunk_syms": c.chunk_syms, "block": c.block, "set_cap": c.set_cap,
+        cands = [{"chunk_syms": c.chunk_syms, "block": c.block, "set_cap": c.set_cap, "wg_per_cu": c.wg_per_cu,
                   "map_slots_log2": c.map_slots_log2, "filter_max_words": c.filter_max_words, "pass_ms": c.pass_ms}
                  for c in rep.cand[:rep.n_candidates]]
         return {"candidates": cands, "best": cands[rep.best] if cands else None, "identical": bool(rep.identical),
                 "from_cache": bool(rep.from_cache)}
 
     def launch(self):
-        a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-        self._check(self._lib.ig_get_launch(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"chunk_syms": a.value, "block": b.value, "set_cap": c.value}
+        a, b, c, w = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(self._lib.ig_get_launch(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(w)))
+        return {"chunk_syms": a.value, "block": b.value, "set_cap": c.value, "wg_per_cu": w.value}
 
-    def set_launch(self, chunk_syms, block, set_cap):
-        self._check(self._lib.ig_set_launch(self._h, chunk_syms, block, set_cap))
+    def set_launch(self, chunk_syms, block, set_cap, wg_per_cu=1):
+        self._check(self._lib.ig_set_launch(self._h, chunk_syms, block, set_cap, wg_per_cu))
 
     def tables(self):
         """The table sizes (ig_get_tables) as a dict."""

@@ -28,6 +28,12 @@ int check_hip(ig_ctx *c, hipError_t e, const char *what) {
   return 1;
 }
 
+// a device buffer back to where it came from (the caller's allocator, or HIP)
+static void free_device(ig_ctx *c, void *p) {
+  if (c->cfg.alloc) c->cfg.free(p, reinterpret_cast<void *>(c->stream), c->cfg.alloc_user);
+  else (void)hipFree(p);
+}
+
 int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
   if (bytes == 0) bytes = 16;
   if (b.p && b.bytes >= bytes) return 0;
@@ -35,7 +41,7 @@ int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
   if (b.p) {
     // the stream may still use the old buffer
     if (check_hip(c, hipStreamSynchronize(c->stream), "sync before realloc")) return IG_EDEVICE;
-    (void)hipFree(b.p);
+    free_device(c, b.p);
     c->held_bytes -= b.bytes;
     b.p = nullptr;
     b.bytes = 0;
@@ -49,11 +55,19 @@ int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
     }
   }
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error(c, IG_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)want, hipGetErrorString(e));
-    return IG_ENOMEM;
+  if (c->cfg.alloc) {
+    p = c->cfg.alloc(want, reinterpret_cast<void *>(c->stream), c->cfg.alloc_user);
+    if (!p) {
+      set_error(c, IG_ENOMEM, "the caller's allocator returned no memory for %llu bytes", (unsigned long long)want);
+      return IG_ENOMEM;
+    }
+  } else {
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error(c, IG_ENOMEM, "hipMalloc(%llu) failed: %s", (unsigned long long)want, hipGetErrorString(e));
+      return IG_ENOMEM;
+    }
   }
   b.p = p;
   b.bytes = want;
@@ -64,7 +78,7 @@ int dev_reserve(ig_ctx *c, DevBuf &b, size_t bytes) {
 
 void dev_release(ig_ctx *c, DevBuf &b) {
   if (b.p) {
-    (void)hipFree(b.p);
+    free_device(c, b.p);
     c->held_bytes -= b.bytes;
   }
   b.p = nullptr;
@@ -166,7 +180,7 @@ int ig_create(const ig_config *cfg, ig_ctx **out) {
   if (!out) return IG_EINVAL;
   *out = nullptr;
   if (!cfg || (cfg->symbol_bits != 8 && cfg->symbol_bits != 2) || (cfg->count_bits != 32 && cfg->count_bits != 64) ||
-      (cfg->freq != IG_FREQ_DOC && cfg->freq != IG_FREQ_OCC))
+      (cfg->freq != IG_FREQ_DOC && cfg->freq != IG_FREQ_OCC) || (!cfg->alloc != !cfg->free))
     return IG_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) {
@@ -383,9 +397,16 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // the other passes assume the largest (256 buckets per wavefront)
   p.hist_words = occ ? 0u : (c->lc.block / 64) * (mode == MODE_FILTERED ? dedup_shape(nc, c->m).nb1 : 256u);
   p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 10u : 0u;   // 8 B key + 2 B step
+  // LDS a workgroup may take: all of a CU's (less static use and slack) with one workgroup per
+  // CU, half of it with two.  Two per CU is a request: a pass whose LDS does not fit half a CU
+  // (with the survivor rings, when it would have them) runs one per CU.
+  const size_t lds_one = 160 * 1024 - 8192, lds_two = 80 * 1024 - 1024;
+  uint32_t wpc = c->lc.grid_per_cu > 1 ? 2u : 1u;
+  if (wpc == 2 && scan_lds_bytes(p, mode, occ) > lds_two) wpc = 1;
+  const size_t lds_budget = wpc == 2 ? lds_two : lds_one;
   // without LDS for the survivor rings the scan resolves survivors in place; so it does when
   // the previous table holds every (n-1)-gram over the alphabet (every window survives)
-  if (p.qbytes && scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192) p.qbytes = 0;
+  if (p.qbytes && scan_lds_bytes(p, mode, occ) > lds_budget) p.qbytes = 0;
   if (p.qbytes) {
     // the compacted scan's thread runs are whole stage words and at most 64 windows long
     const uint64_t spd = 32 / b, span_max = c->lc.chunk_syms + 128 / b - 1;
@@ -396,11 +417,11 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
     if (space <= c->kept) p.qbytes = 0;
   }
-  if (scan_lds_bytes(p, mode, occ) > 160 * 1024 - 8192)
+  if (scan_lds_bytes(p, mode, occ) > lds_budget)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
                      (unsigned long long)scan_lds_bytes(p, mode, occ));
   const uint32_t block = c->lc.block;
-  const uint32_t grid = (uint32_t)c->n_cu * c->lc.grid_per_cu;
+  const uint32_t grid = (uint32_t)c->n_cu * wpc;
   c->last.chunk_syms = c->lc.chunk_syms;
   c->last.block = block;
   c->last.grid = grid;

@@ -28,9 +28,10 @@ static std::string tune_key(ig_ctx *c, uint32_t n, uint64_t k_keep) {
 
 // A launch shape the scan supports: whole wavefronts per workgroup, a power-of-two LDS set of at
 // least one slot per thread (the set's hashing and its flush assume both), chunk length in range.
-static bool shape_ok(uint32_t chunk_syms, uint32_t block, uint32_t set_cap) {
+static bool shape_ok(uint32_t chunk_syms, uint32_t block, uint32_t set_cap, uint32_t wg_per_cu) {
   return chunk_syms >= 1024 && chunk_syms <= 65536 && (block == 256 || block == 512 || block == 1024) &&
-         set_cap >= 1024 && set_cap <= 32768 && (set_cap & (set_cap - 1)) == 0 && set_cap >= block;
+         set_cap >= 1024 && set_cap <= 32768 && (set_cap & (set_cap - 1)) == 0 && set_cap >= block &&
+         (wg_per_cu == 1 || wg_per_cu == 2);
 }
 
 // The last line for `key` whose shape is valid (a stale or edited line is ignored).
@@ -43,12 +44,13 @@ static bool cache_lookup(const std::string &key, LaunchCfg *lc) {
   bool found = false;
   while (fgets(line, sizeof line, f)) {
     char k[600];
-    unsigned cs, bl, sc, ml, fw;
-    if (sscanf(line, "%599s %u %u %u %u %u", k, &cs, &bl, &sc, &ml, &fw) == 6 && key == k && shape_ok(cs, bl, sc) &&
-        ml >= 1 && ml <= 3 && fw >= 1024 && fw <= 16384 && (fw & (fw - 1)) == 0) {
+    unsigned cs, bl, sc, wp, ml, fw;
+    if (sscanf(line, "%599s %u %u %u %u %u %u", k, &cs, &bl, &sc, &wp, &ml, &fw) == 7 && key == k &&
+        shape_ok(cs, bl, sc, wp) && ml >= 1 && ml <= 3 && fw >= 1024 && fw <= 16384 && (fw & (fw - 1)) == 0) {
       lc->chunk_syms = cs;
       lc->block = bl;
       lc->set_cap = sc;
+      lc->grid_per_cu = wp;
       lc->map_log2 = ml;
       lc->filt_max_words = fw;
       found = true;
@@ -63,7 +65,8 @@ static void cache_store(const std::string &key, const LaunchCfg &lc) {
   if (!path) return;
   FILE *f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s %u %u %u %u %u\n", key.c_str(), lc.chunk_syms, lc.block, lc.set_cap, lc.map_log2, lc.filt_max_words);
+  fprintf(f, "%s %u %u %u %u %u %u\n", key.c_str(), lc.chunk_syms, lc.block, lc.set_cap, lc.grid_per_cu, lc.map_log2,
+          lc.filt_max_words);
   fclose(f);
 }
 
@@ -91,6 +94,7 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
       rep->cand[0].chunk_syms = cached.chunk_syms;
       rep->cand[0].block = cached.block;
       rep->cand[0].set_cap = cached.set_cap;
+      rep->cand[0].wg_per_cu = cached.grid_per_cu;
       rep->cand[0].map_slots_log2 = cached.map_log2;
       rep->cand[0].filter_max_words = cached.filt_max_words;
       rep->cand[0].pass_ms = -1.0;
@@ -174,6 +178,7 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
     rep->cand[nrep].chunk_syms = lc.chunk_syms;
     rep->cand[nrep].block = lc.block;
     rep->cand[nrep].set_cap = lc.set_cap;
+    rep->cand[nrep].wg_per_cu = lc.grid_per_cu;
     rep->cand[nrep].map_slots_log2 = lc.map_log2;
     rep->cand[nrep].filter_max_words = lc.filt_max_words;
     rep->cand[nrep].pass_ms = ms;
@@ -218,6 +223,27 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
         win_idx = nrep - 1;
       }
     }
+  // stage 3: two workgroups per CU (twice the wavefronts to hide probe latency), which needs a
+  // workgroup's LDS to fit half a CU: the Bloom image in L2 (an LDS cap of 1024 words sends it
+  // there) and a shorter chunk with a smaller LDS set
+  for (uint32_t cs : {12288u, 16384u})
+    for (uint32_t ml : {1u, 2u}) {
+      LaunchCfg lc = win;
+      lc.chunk_syms = cs;
+      lc.block = 1024;
+      lc.set_cap = 4096;
+      lc.grid_per_cu = 2;
+      lc.map_log2 = ml;
+      lc.filt_max_words = 1024;
+      const double ms = trial(lc);
+      if (ms <= -2.0) return restore((int)(ms + 2.0), nullptr);
+      record(lc, ms);
+      if (ms >= 0 && ms < best_ms) {
+        best_ms = ms;
+        win = lc;
+        win_idx = nrep - 1;
+      }
+    }
   // the winner's chunks and index
   {
     const LaunchCfg now = c->lc;
@@ -238,18 +264,21 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
   return IG_OK;
 }
 
-extern "C" int ig_get_launch(const ig_ctx *c, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap) {
+extern "C" int ig_get_launch(const ig_ctx *c, uint32_t *chunk_syms, uint32_t *block, uint32_t *set_cap,
+                             uint32_t *wg_per_cu) {
   if (!c) return IG_EINVAL;
   if (chunk_syms) *chunk_syms = c->lc.chunk_syms;
   if (block) *block = c->lc.block;
   if (set_cap) *set_cap = c->lc.set_cap;
+  if (wg_per_cu) *wg_per_cu = c->lc.grid_per_cu;
   return IG_OK;
 }
 
-extern "C" int ig_set_launch(ig_ctx *c, uint32_t chunk_syms, uint32_t block, uint32_t set_cap) {
+extern "C" int ig_set_launch(ig_ctx *c, uint32_t chunk_syms, uint32_t block, uint32_t set_cap, uint32_t wg_per_cu) {
   if (!c) return IG_EINVAL;
   if (c->server) return set_error(c, IG_ESTATE, "serving loop is running");
-  if (!shape_ok(chunk_syms, block, set_cap)) return set_error(c, IG_EINVAL, "bad launch shape");
+  if (!shape_ok(chunk_syms, block, set_cap, wg_per_cu)) return set_error(c, IG_EINVAL, "bad launch shape");
+  c->lc.grid_per_cu = wg_per_cu;
   const bool rechunk = chunk_syms != c->lc.chunk_syms;
   c->lc.chunk_syms = chunk_syms;
   c->lc.block = block;

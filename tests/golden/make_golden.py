@@ -1,11 +1,13 @@
 """Write expected pass tables for full-size workloads, computed by the CPU oracle only.
 
-Usage: python tests/golden/make_golden.py WORKLOAD [--threads T] [--m M]
+Usage: python tests/golden/make_golden.py WORKLOAD [--threads T] [--m M] [--table-out FILE.npz]
 
 For each pass of the chain (n = 1..N, k_keep = K, Eq. 2 frequency) it stores
 the kept length, the SHA-256 of the ordered table (little-endian uint64 triples
 key_lo, key_hi, count) and the first and last entries, plus the corpus digest,
-in tests/golden/workload<W>.json.  Nothing here reads the HIP library.
+in tests/golden/workload<W>.json.  With --table-out, the last pass's whole ordered table (keys as
+uint64 (lo, hi) pairs and counts) also goes to a compressed .npz file.  Nothing here reads the HIP
+library.
 """
 import argparse
 import hashlib
@@ -44,6 +46,7 @@ def main():
     ap.add_argument("--threads", type=int, default=os.cpu_count())
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--table-out", default=None, help="npz file for the last pass's ordered table")
     a = ap.parse_args()
     nmax, k_keep = CHAINS[a.workload]
     corpus = gen.workload(a.workload, m=a.m, nthreads=a.threads)
@@ -65,6 +68,11 @@ def main():
         print("workload %d pass %d kept %d %.1fs" % (a.workload, n, k, time.time() - t0), flush=True)
         with open(out, "w") as fh:
             json.dump(rec, fh, indent=1)
+    if a.table_out:
+        keys, counts = o.topk()
+        np.savez_compressed(a.table_out, keys=np.ascontiguousarray(keys, np.uint64),
+                            counts=np.ascontiguousarray(counts, np.uint64), n=np.uint32(nmax),
+                            k_keep=np.uint64(k_keep), workload=np.uint32(a.workload))
 
 
 if __name__ == "__main__":

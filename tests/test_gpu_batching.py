@@ -36,7 +36,8 @@ def test_graph_replays_match_eager_and_oracle():
         g.featurize(q)                         # eager work between replays
 
 
-@pytest.mark.parametrize("shape", [(8192, 256, 4096), (16384, 1024, 8192), (32768, 512, 8192), (4096, 512, 1024)])
+@pytest.mark.parametrize("shape", [(8192, 256, 4096), (16384, 1024, 8192), (32768, 512, 8192), (4096, 512, 1024),
+                                   (16384, 1024, 4096, 2), (12288, 1024, 4096, 2)])
 def test_launch_shapes_same_result(shape):
     corpus = gen.workload(2, m=40)
     ns = list(range(1, 6))
@@ -44,6 +45,8 @@ def test_launch_shapes_same_result(shape):
     exp, _ = oracle_tables(corpus, ns, 20000)
     g = ig.Intergrams()
     g.set_launch(*shape)
+    if len(shape) == 4 and shape[3] == 2:
+        g.set_tables(filter_max_words=1024)   # two workgroups per CU: the Bloom image stays in L2
     got, _ = gpu_tables(corpus, ns, 20000, ctx=g)
     assert_tables_equal(got, exp, "shape %s" % (shape,))
 
