@@ -301,6 +301,8 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=64)
     ap.add_argument("--configs", default="1,3,4",
                     help="other workloads whose whole chain is timed pass by pass (comma list; '' to skip)")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="time only the --configs chains (for profiling them; prints their JSON, not the benchmark line)")
     ap.add_argument("--saturation-requests", type=int, default=20000,
                     help="requests of the closed-loop serving saturation run (0: skip)")
     a = ap.parse_args()
@@ -325,6 +327,11 @@ def main():
     import paper_2511_14955_amd as ig
 
     threads = min(16, os.cpu_count() or 1)
+    if a.configs_only:
+        out = {str(w): config_chain(ig, w, threads, tune_at={3: 8, 4: 16}.get(w))
+               for w in [int(x) for x in a.configs.split(",") if x.strip()]}
+        print(json.dumps({"configs": out}), flush=True)
+        return
     t0 = time.time()
     corpus = gen.workload(2, m=a.m, nthreads=threads)
     log("workload 2: %d files, %d bytes, generated in %.1fs" % (corpus.m, corpus.nbytes, time.time() - t0))

@@ -90,11 +90,13 @@ __device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t l
 }
 
 // LDS open-addressing set of candidate ids: 1 = newly inserted, 0 = present, -1 = full.
-// The home slot is the top bits of cid times an odd constant (one multiply; the candidate ids of a
-// chunk are dense ranks times sigma plus a code, which the product spreads over the top bits).
+// The home slot is the top bits of a 24 x 24-bit product (a full-rate multiply): the candidate
+// ids of a chunk are dense ranks times sigma plus a code, and the product spreads them over the
+// top bits; ids of 24 bits and more fold their high bits in first.  HIP's __umul24 returns a
+// signed int: the product is shifted as unsigned, or a set top bit would make the slot negative.
 __device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t capshift, uint32_t cid,
                                           uint32_t *slot_out) {
-  uint32_t h = (cid * 0x9E3779B1u) >> capshift;
+  uint32_t h = static_cast<uint32_t>(__umul24(cid ^ (cid >> 20), 0x9E3779u)) >> capshift;
   for (int i = 0; i < 64; i++) {
     const uint32_t cur = atomicCAS(s_set + h, LDS_EMPTY, cid);
     if (cur == LDS_EMPTY) { *slot_out = h; return 1; }
