@@ -2,13 +2,17 @@
 
 - The binary-like corpus (16,384 files, ~3.24 GB, n = 1..8, k_keep = 1e5):
   every pass's ordered table equals the oracle's, by the SHA-256 digests and
-  head/tail entries that tests/golden/make_golden.py wrote from the oracle.
+  head/tail entries that tests/golden/make_golden.py wrote from the oracle;
+  then 600 requests of the serving workload, featurized through the serving
+  loop against that n = 8 table, equal the oracle's rows against its own
+  stored table.
 - The text-like (4 GiB, n = 1..16, k_keep = 1e6, 128-bit keys) and genomic
-  (2-bit, n = 1..31, k_keep = 1e6) corpora are too large for the oracle in a
-  test; they are checked by properties that hold at any size (order, Eq. 2
-  bounds, prefix closure and anti-monotonicity of the chain, the exact pass-1
-  table) and by exact document counts of sampled grams, kept and not kept,
-  found by brute-force substring search over the files.
+  (2-bit, n = 1..31, k_keep = 1e6) corpora take the oracle hours, so their
+  expected tables are the digests make_golden.py stored (every pass equal to the
+  oracle's, where the file exists); they are also checked by properties that
+  hold at any size (order, Eq. 2 bounds, prefix closure and anti-monotonicity of
+  the chain, the exact pass-1 table) and by exact document counts of sampled
+  grams, kept and not kept, found by brute-force substring search over the files.
 """
 import json
 import os
@@ -64,7 +68,44 @@ def test_workload2_full_chain_matches_golden(golden_dir):
         g.rewind()
         g.pass_(8, k)
         check(8, "pass 8 replay %d" % r)
+    _serving_rows_match_oracle(g, golden_dir, gold)
     g.close()
+
+
+def _serving_rows_match_oracle(g, golden_dir, gold, requests=600):
+    """The serving workload's featurize requests (the first `requests` of its stream, files
+    generated like the corpus's) against this n = 8, k = 1e5 table, through the serving loop,
+    equal the oracle's featurization against the oracle's own table for this pass (stored by
+    make_golden.py --table-out)."""
+    import oracle
+    path = os.path.join(golden_dir, "workload2_n8_table.npz")
+    with np.load(path, allow_pickle=False) as z:
+        okeys, ocounts = z["keys"], z["counts"]
+    exp = gold["passes"]["8"]
+    assert table_digest(okeys, ocounts) == exp["sha256"], "stored table is not the pass-8 golden table"
+    o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=min(16, os.cpu_count() or 1))
+    o.set_retained(8, oracle.keys_to_int(okeys), ocounts)
+    rs = gen.RequestStream()
+    files = [rs.file(i) for i in range(requests)]
+    say("serving: %d requests of the request stream (%d bytes) against the n=8 table" % (
+        requests, sum(len(f) for f in files)))
+    ip, ind = o.featurize(gen.from_files(files))
+    g.serve_start(max_inflight_bytes=2 << 30, n_streams=4, max_batch=16)
+    try:
+        for i, f in enumerate(files):
+            assert g.submit(ig.REQ_FEATURIZE, f, np.array([0, len(f)], np.uint64), tag=i) == ig.IG_OK
+        got = {}
+        t_end = time.time() + 120
+        while len(got) < requests:
+            for r in g.poll():
+                got[r["tag"]] = r
+            assert time.time() < t_end
+    finally:
+        g.serve_stop()
+    for i in range(requests):
+        assert got[i]["status"] == ig.IG_OK
+        assert np.array_equal(got[i]["cols"], ind[int(ip[i]):int(ip[i + 1])]), "request %d" % i
+    say("serving: %d rows equal the oracle's (%d entries)" % (requests, len(ind)))
 
 
 # ---------------------------------------------------------------- properties
@@ -195,12 +236,31 @@ def _pass1_exact(buf, offs, keys, counts, k, what):
 
 
 @pytest.mark.parametrize("workload,nmax,k,sample_ns", [(3, 16, 1000000, [2, 16]), (4, 31, 1000000, [2, 31])])
-def test_full_size_properties_and_samples(workload, nmax, k, sample_ns):
+def test_full_size_properties_and_samples(golden_dir, workload, nmax, k, sample_ns):
     t0 = time.time()
     corpus = gen.workload(workload, nthreads=min(16, os.cpu_count() or 1))
     say("workload %d full size: %d sequences, %d bytes (%.1fs)" % (workload, corpus.m, corpus.nbytes, time.time() - t0))
     tables = _run_chain(corpus, nmax, k)
     say("workload %d: chain n=1..%d done (%.1fs)" % (workload, nmax, time.time() - t0))
+    # the oracle's digests of every pass, where make_golden.py has written them
+    gpath = os.path.join(golden_dir, "workload%d.json" % workload)
+    if os.path.exists(gpath):
+        with open(gpath) as fh:
+            gold = json.load(fh)
+        assert corpus.m == gold["m"] and corpus.nbytes == gold["bytes"] and corpus.sha256() == gold["corpus_sha256"]
+        # make_golden.py writes the passes in order as the oracle finishes them: every pass the
+        # file holds is compared (all of the chain once it is complete)
+        ng = len(gold["passes"])
+        assert gold["k_keep"] == k and 1 <= ng <= nmax and sorted(map(int, gold["passes"])) == list(range(1, ng + 1)), \
+            "golden file for a different chain"
+        for n in range(1, ng + 1):
+            keys, counts = tables[n - 1]
+            exp = gold["passes"][str(n)]
+            assert len(counts) == exp["kept"], "workload %d pass %d: kept %d vs %d" % (workload, n, len(counts), exp["kept"])
+            for i, (key, c) in enumerate(exp["head"]):
+                assert (_key_int(keys, i), int(counts[i])) == (int(key), c), (workload, n, i)
+            assert table_digest(keys, counts) == exp["sha256"], "workload %d pass %d digest" % (workload, n)
+        say("workload %d: passes 1..%d of %d equal the oracle's digests (%.1fs)" % (workload, ng, nmax, time.time() - t0))
     bits = corpus.symbol_bits
     for n in range(1, nmax + 1):
         keys, counts = tables[n - 1]
