@@ -343,7 +343,15 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     return set_error(c, IG_EOVERFLOW, "W_n = %llu windows need 64-bit counts", (unsigned long long)W);
   if (hipSetDevice(c->cfg.device) != hipSuccess) return set_error(c, IG_EDEVICE, "hipSetDevice");
   hipStream_t s = c->stream;
-  const int mode = filtered ? MODE_FILTERED : ((uint64_t)n * b <= 26 ? MODE_DENSE : MODE_SPARSE);
+  int mode = filtered ? MODE_FILTERED : ((uint64_t)n * b <= 26 ? MODE_DENSE : MODE_SPARSE);
+  // The previous pass kept every (n-1)-gram over the alphabet (kept = sigma^(n-1)): every window
+  // passes Algorithm 3's prefix test, so the pass is the unfiltered count of all n-grams, and it
+  // is direct-indexed when its keys fit (no prefix lookup per window).
+  if (filtered && (uint64_t)n * b <= 26) {
+    uint64_t space = 1;
+    for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
+    if (space <= c->kept) mode = MODE_DENSE;
+  }
   const int kw = (uint64_t)n * b > 64 ? 2 : 1;
   const int count64 = occ && W >= 0xFFFFFFFFull ? 1 : 0;
   const uint32_t cbits = (uint32_t)count_bits_for(occ ? std::max<uint64_t>(W, 1) : std::max<uint64_t>(c->m, 1));

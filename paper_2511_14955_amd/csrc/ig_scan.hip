@@ -89,7 +89,8 @@ __device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t l
   return 0xFFFFFFFFu;
 }
 
-// LDS open-addressing set of candidate ids: 1 = newly inserted, 0 = present, -1 = full.
+// LDS open-addressing set of candidate ids: 1 = newly inserted, 0 = present, -1 = full (no
+// free slot within 32 probes).
 // The home slot is the top bits of a 24 x 24-bit product (a full-rate multiply): the candidate
 // ids of a chunk are dense ranks times sigma plus a code, and the product spreads them over the
 // top bits; ids of 24 bits and more fold their high bits in first.  HIP's __umul24 returns a
@@ -97,7 +98,7 @@ __device__ __forceinline__ uint32_t table_insert(const ScanParams &p, uint64_t l
 __device__ __forceinline__ int lds_insert(uint32_t *s_set, uint32_t capmask, uint32_t capshift, uint32_t cid,
                                           uint32_t *slot_out) {
   uint32_t h = static_cast<uint32_t>(__umul24(cid ^ (cid >> 20), 0x9E3779u)) >> capshift;
-  for (int i = 0; i < 64; i++) {
+  for (int i = 0; i < 32; i++) {
     const uint32_t cur = atomicCAS(s_set + h, LDS_EMPTY, cid);
     if (cur == LDS_EMPTY) { *slot_out = h; return 1; }
     if (cur == cid) { *slot_out = h; return 0; }
@@ -121,6 +122,7 @@ template <int B, int KW, int MODE, int OCC, typename CT, int CMP, int FEAT>
 __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ uint32_t s_nrec;          // Eq. 2: records written by this chunk
+  __shared__ uint32_t s_full;          // the chunk's LDS set refused an insert: bypass it
   uint8_t *s_stage = lds;
   uint32_t *s_filt = reinterpret_cast<uint32_t *>(lds + p.stage_bytes);
   // the filter image is padded to 16 bytes, so that the 8-byte ring entries below stay aligned
@@ -142,11 +144,14 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
 
   const uint32_t tid = threadIdx.x, bs = blockDim.x;
   const uint32_t n = p.n;
+  // Eq. 2 with survivor rings: each drain records its candidates new to the chunk as it inserts them
+  constexpr bool EAI = CMP != 0 && !OCC && !FEAT;
   const uint32_t nb = n * B;
   const uint64_t mlo = (KW == 1) ? (nb >= 64 ? ~0ull : ((1ull << nb) - 1)) : ~0ull;
   const uint64_t mhi = (KW == 2) ? (nb >= 128 ? ~0ull : ((1ull << (nb - 64)) - 1)) : 0ull;
+  // the LDS set's buckets (set_cap / 4, a power of two)
   const uint32_t capmask = p.set_cap - 1;
-  const uint32_t capshift = 32u - (uint32_t)__builtin_ctz(p.set_cap);   // set_cap is a power of two
+  const uint32_t capshift = 32u - (uint32_t)__builtin_ctz(p.set_cap);
   const uint32_t fmask = p.filt_words - 1;
 
   if (MODE == MODE_FILTERED)
@@ -161,7 +166,10 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   }
   for (uint32_t i = tid; i < 256; i += bs) s_code[i] = p.code[i];
   for (uint32_t i = tid; i < p.hist_words; i += bs) s_h1w[i] = 0;
-  if (tid == 0) s_nrec = 0;
+  if (tid == 0) {
+    s_nrec = 0;
+    s_full = 0;
+  }
   __syncthreads();
   const uint32_t lane = tid & 63, nwaves = bs >> 6;
   const uint64_t lanes_below = (1ull << lane) - 1;
@@ -269,20 +277,30 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       uint32_t *gbm = FEAT ? p.bitmaps + (uint64_t)c.file * p.fwords : nullptr;
       // one surviving candidate: de-duplicate in the chunk's LDS set (FEAT: cid is the rank, whose
       // bit is set in the sequence's bitmap)
-      auto handle = [&](uint32_t cid) {
+      // (returns the set insert's result: 1 when cid is new to the chunk)
+      auto handle = [&](uint32_t cid) -> int {
         if constexpr (FEAT) {
           if (p.lds_bitmap) atomicOr(s_bm + (cid >> 5), 1u << (cid & 31));
           else atomicOr(gbm + (cid >> 5), 1u << (cid & 31));
-          return;
+          return 0;
         }
+        // A chunk with more distinct candidates than the set holds would probe a full set for
+        // every later window: once an insert has failed, the rest of the chunk goes straight to
+        // the counters (Eq. 1) or to records (Eq. 2; a record may repeat one of the set's, which
+        // the once-per-sequence count allows).
         uint32_t slot;
-        const int ins = lds_insert(s_set, capmask, capshift, cid, &slot);
+        int ins = -1;
+        if (!__hip_atomic_load(&s_full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+          ins = lds_insert(s_set, capmask, capshift, cid, &slot);
+          if (ins < 0) __hip_atomic_store(&s_full, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         if (OCC) {
           if (ins >= 0) atomicAdd(s_cnt + slot, 1u);
           else cnt_add<CT>(p.cnt, cid, (CT)1);
         } else if (ins < 0) {
           emit(wbeg, cid);
         }
+        return ins;
       };
       if constexpr (CMP != 0) {
         // About a third of the windows pass the filter, so nearly every wavefront has a
@@ -319,6 +337,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           bool again = false;
           uint64_t key = 0;
           uint32_t dnext = 0;
+          uint32_t newcid = LDS_EMPTY;   // Eq. 2: a candidate new to the chunk, recorded below
           if (lane < cnt) {
             key = q[(head + lane) & (SCAN_QCAP - 1)];
             const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
@@ -358,9 +377,24 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
                 v = p.map[slot];
               }
             }
-            if (cid != LDS_EMPTY) handle(cid);
+            if (cid != LDS_EMPTY && handle(cid) == 1) newcid = cid;
           }
           head += cnt;
+          if constexpr (EAI) {
+            // the drain's new candidates become records at once, at consecutive slots (one LDS
+            // atomic per wavefront), so the chunk's end only clears the set
+            const uint64_t nm = __ballot(newcid != LDS_EMPTY);
+            if (nm) {
+              const uint32_t leader = (uint32_t)__ffsll((unsigned long long)nm) - 1;
+              uint32_t base = 0;
+              if (lane == leader) base = atomicAdd(&s_nrec, (uint32_t)__popcll(nm));
+              base = __shfl(base, leader);
+              if (newcid != LDS_EMPTY) {
+                __builtin_nontemporal_store(newcid, p.rec + wbeg + base + (uint32_t)__popcll(nm & lanes_below));
+                atomicAdd(my_h1 + (p.low1 >= 32 ? 0u : (newcid >> p.low1)), 1u);
+              }
+            }
+          }
           // requeue behind the live entries: at most 63 + cnt <= 127 entries are live afterwards
           const uint64_t m = __ballot(again);
           if (again) {
@@ -585,8 +619,14 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         }
       }
     }
+    // records made at insert time: the set is only cleared
+    if (EAI) {
+      typedef uint32_t u32x4e_t __attribute__((ext_vector_type(4)));
+      for (uint32_t i = tid; i < p.set_cap / 4; i += bs)
+        reinterpret_cast<u32x4e_t *>(s_set)[i] = u32x4e_t{LDS_EMPTY, LDS_EMPTY, LDS_EMPTY, LDS_EMPTY};
+    }
     // set_cap is a multiple of the block, so every lane of a wavefront runs the same iterations
-    for (uint32_t i = tid; !FEAT && i < p.set_cap; i += bs) {
+    for (uint32_t i = tid; !FEAT && !EAI && i < p.set_cap; i += bs) {
       const uint32_t cid = s_set[i];
       const bool full = cid != LDS_EMPTY;
       if (OCC) {
@@ -611,6 +651,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       }
     }
     __syncthreads();
+    if (tid == 0) s_full = 0;
     if (!OCC && !FEAT) {
       if (tid == 0) {
         p.nrec[c.fci] = s_nrec;
