@@ -208,7 +208,7 @@ CHAINS = {  # workload -> (symbol bits, last n, k_keep, count bits)
 }
 
 
-def config_chain(ig, workload, threads, reps=3, tune_at=None):
+def config_chain(ig, workload, threads, reps=3, tune_at=None, fixed=None):
     """Every pass of a workload's chain (n = 1..N, k_keep fixed, Eq. 2) on one GPU: the device
     time of each pass (median of `reps` runs, rewinding between them; graph-captured), its input
     rate and window rate.  tune_at: pass whose launch shape and table sizes the autotuner picks
@@ -220,6 +220,9 @@ def config_chain(ig, workload, threads, reps=3, tune_at=None):
     log("workload %d: %d sequences, %d bytes, generated in %.1fs" % (workload, corpus.m, corpus.nbytes, time.time() - t0))
     g = ig.Intergrams(symbol_bits=bits, freq=ig.FREQ_DOC, count_bits=cbits)
     g.load(corpus)
+    if fixed:
+        g.set_launch(fixed[0], fixed[1], fixed[2], wg_per_cu=fixed[3])
+        g.set_tables(map_slots_log2=fixed[4], filter_max_words=fixed[5])
     rows, tune = [], None
     t_chain = time.time()
     for n in range(1, nmax + 1):
@@ -303,6 +306,9 @@ def main():
                     help="other workloads whose whole chain is timed pass by pass (comma list; '' to skip)")
     ap.add_argument("--configs-only", action="store_true",
                     help="time only the --configs chains (for profiling them; prints their JSON, not the benchmark line)")
+    ap.add_argument("--configs-launch", default=None,
+                    help="with --configs-only: fixed launch shape and table sizes CHUNK,BLOCK,SETCAP,WG_PER_CU,MAP,FILTWORDS "
+                         "for the chains instead of the autotuner")
     ap.add_argument("--saturation-requests", type=int, default=20000,
                     help="requests of the closed-loop serving saturation run (0: skip)")
     a = ap.parse_args()
@@ -328,7 +334,8 @@ def main():
 
     threads = min(16, os.cpu_count() or 1)
     if a.configs_only:
-        out = {str(w): config_chain(ig, w, threads, tune_at={3: 8, 4: 16}.get(w))
+        fixed = [int(x) for x in a.configs_launch.split(",")] if a.configs_launch else None
+        out = {str(w): config_chain(ig, w, threads, tune_at=None if fixed else {3: 8, 4: 16}.get(w), fixed=fixed)
                for w in [int(x) for x in a.configs.split(",") if x.strip()]}
         print(json.dumps({"configs": out}), flush=True)
         return

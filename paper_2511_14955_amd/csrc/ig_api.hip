@@ -626,7 +626,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
             if (x) (void)hipGraphExecDestroy(x);
           return IG_EDEVICE;
         }
-        if (c->graphs.size() >= 8) {
+        // up to 32 captured passes: a whole chain (n <= 31 for 2-bit symbols) replays from the cache
+        if (c->graphs.size() >= 32) {
           for (auto &x : c->graphs.front().exec)
             if (x) (void)hipGraphExecDestroy(x);
           c->graphs.erase(c->graphs.begin());
