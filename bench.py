@@ -116,18 +116,28 @@ def cpu_model():
     return None
 
 
-def cpu_baseline(n, k_keep, sample_files, threads):
-    """The CPU oracle as it stands, on the first sample_files files of the same corpus."""
+def cpu_baseline(n, k_keep, sample_files, threads, target_s=10.0):
+    """The CPU oracle as it stands, on the first files of the same corpus: first sample_files of
+    them, then, if that pass took well under target_s, as many as should take about target_s
+    (at most the whole corpus)."""
     import gen
     import oracle
-    corpus = gen.workload(2, m=sample_files, nthreads=threads)
-    o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=threads)
-    o.load(corpus)
-    for j in range(1, n):
-        assert o.pass_(j, k_keep) == 0
-    t0 = time.perf_counter()
-    assert o.pass_(n, k_keep) == 0
-    dt = time.perf_counter() - t0
+
+    def timed(files):
+        corpus = gen.workload(2, m=files, nthreads=threads)
+        o = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=threads)
+        o.load(corpus)
+        for j in range(1, n):
+            assert o.pass_(j, k_keep) == 0
+        t0 = time.perf_counter()
+        assert o.pass_(n, k_keep) == 0
+        return corpus, time.perf_counter() - t0
+
+    m_all = gen.default_m(2)
+    corpus, dt = timed(sample_files)
+    if dt < target_s / 2 and sample_files < m_all:
+        sample_files = min(m_all, max(sample_files + 1, int(sample_files * target_s / max(dt, 1e-3))))
+        corpus, dt = timed(sample_files)
     # one thread on the tiny plain run (64 files x 64 KiB, n = 1..4, k = 1000)
     tiny = gen.workload(1)
     o1 = oracle.Oracle(8, oracle.FREQ_DOC, nthreads=1)
