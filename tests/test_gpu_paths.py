@@ -6,6 +6,9 @@
   590K kept grams): the rank bits then go straight to the sequence's bitmap in HBM.
 - Eq. 1 with 64-bit device counters (more than 2^32 windows), checked against closed forms,
   and 32-bit counts refused there with IG_EOVERFLOW.
+- A chunk with more distinct candidates than its LDS set holds (the set is bypassed for the
+  rest of the chunk), and a pass run as the direct-indexed count inside a chain because the
+  previous pass kept every (n-1)-gram of the alphabet.
 """
 import time
 
@@ -154,5 +157,38 @@ def test_occ_64bit_counters_and_eoverflow():
             assert sum(c for _, c in want) > (1 << 32) - 8
             assert [(int(keys[i, 0]), int(counts[i])) for i in range(len(counts))] == want, "pass %d" % n
             assert int(keys[:, 1].max()) == 0
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("occ", [False, True])
+def test_set_overflow_bypass_and_dense_chain_pass(occ):
+    """Random bytes: pass 1 keeps all 256 symbols, so pass 2 is the direct-indexed count of all
+    2-grams inside the chain; pass 3 (k = 60,000 prefixes) has far more distinct candidates per
+    chunk than the chunk's LDS set holds, so its chunks fill the set and bypass it (straight to
+    the counters for Eq. 1, to records for Eq. 2).  Every table equals the oracle's."""
+    rng = np.random.default_rng(2027 + occ)
+    files = [rng.integers(0, 256, size=int(rng.integers(150_000, 300_000)), dtype=np.uint8) for _ in range(8)]
+    corpus = gen.from_files(files, 8)
+    ns, k = [1, 2, 3], 60_000
+    say("set overflow + dense chain pass: 8 random-byte files, n=1..3, k=%d, %s" % (k, "Eq. 1" if occ else "Eq. 2"))
+    exp, _ = oracle_tables(corpus, ns, k, occ)
+    g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_OCC if occ else ig.FREQ_DOC)
+    try:
+        g.load(corpus)
+        lc = g.launch()
+        got = []
+        for n in ns:
+            g.pass_(n, k)
+            keys, counts = g.topk()
+            got.append((keys.copy(), counts.copy()))
+            st = g.last_stats()
+            if n == 1:
+                assert g.table_info()[1] == 256
+            if n == 3 and not occ:
+                # more records than the sets of all chunks could hold: the set was bypassed
+                nchunks = sum((len(f) + lc["chunk_syms"] - 1) // lc["chunk_syms"] for f in files)
+                assert st["records"] > nchunks * lc["set_cap"], (st["records"], nchunks, lc)
+        assert_tables_equal(got, exp, "random bytes")
     finally:
         g.close()
