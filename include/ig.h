@@ -193,6 +193,9 @@ typedef struct {
   uint32_t grid;
   uint64_t records;      /* Eq. 2: chunk-distinct (candidate, sequence) records counted once per sequence */
   double   dedup_ms;     /* Eq. 2: counting the records once per sequence */
+  uint32_t set_cap;      /* the scan's LDS set size in use: the launch's, halved while it did not
+                            fit this pass's LDS (results do not depend on it) */
+  uint32_t reserved;
 } ig_pass_stats;
 int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
 
@@ -213,11 +216,16 @@ const char *ig_last_error(const ig_ctx *ctx);
  * set_cap: LDS de-duplication set entries (a power of two, 1024..32768, at
  * least block); wg_per_cu: scan workgroups per compute unit (1 or 2; a pass
  * whose workgroup LDS does not fit half a CU runs one per CU).
- * IG_EINVAL otherwise.  The shape changes speed only, never results.
+ * IG_EINVAL otherwise.  The shape changes speed only, never results.  A pass
+ * whose LDS cannot hold the shape (its filter image, survivor rings and
+ * histograms depend on the pass) first resolves survivors without the rings,
+ * then halves the set until it fits (down to block entries); ig_last_pass_stats
+ * reports the set size the pass ran with.
  *
  * ig_autotune runs pass n on the loaded corpus for each candidate shape
  * (rewinding after each), checks that all candidates return the same table,
- * and keeps the fastest; the chain state is left as it was.  It searches the
+ * and keeps the fastest (a shape that runs only with a smaller LDS set counts as
+ * unusable for the pass); the chain state is left as it was.  It searches the
  * launch shape first, then, with the best one, the table sizes of
  * ig_set_tables (map_slots_log2 1 or 2, filter_max_words 8192 or 16384),
  * which apply to the current table's index, and last two workgroups per CU
@@ -246,7 +254,7 @@ int ig_set_launch(ig_ctx *ctx, uint32_t chunk_syms, uint32_t block, uint32_t set
  *
  *  map_slots_log2:      the exact maps over a retained table of k keys (key -> rank, and the
  *                       quotient map) get the smallest power of two >= k << map_slots_log2
- *                       slots: load at most 1/2, 1/4, 1/8 for 1, 2, 3 (default 1).
+ *                       slots: load at most 1/2, 1/4, 1/8 for 1, 2, 3 (default 2).
  *  filter_bits_per_key: the Bloom filter image a scan workgroup holds in LDS gets about this
  *                       many bits per retained key (4..32, default 12), a power of two of at
  *                       most filter_max_words 32-bit words (1024..16384, default 16384).

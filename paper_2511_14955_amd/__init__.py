@@ -54,7 +54,8 @@ class ig_pass_stats(ctypes.Structure):
     _fields_ = [("pass_ms", ctypes.c_double), ("scan_ms", ctypes.c_double), ("select_ms", ctypes.c_double),
                 ("windows", ctypes.c_uint64), ("distinct", ctypes.c_uint64), ("input_bytes", ctypes.c_uint64),
                 ("replays", ctypes.c_uint32), ("chunk_syms", ctypes.c_uint32), ("block", ctypes.c_uint32),
-                ("grid", ctypes.c_uint32), ("records", ctypes.c_uint64), ("dedup_ms", ctypes.c_double)]
+                ("grid", ctypes.c_uint32), ("records", ctypes.c_uint64), ("dedup_ms", ctypes.c_double),
+                ("set_cap", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class _tune_cand(ctypes.Structure):

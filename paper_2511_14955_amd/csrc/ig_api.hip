@@ -425,11 +425,17 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
     if (space <= c->kept) p.qbytes = 0;
   }
+  // A shape whose LDS set does not fit this pass (say a shape tuned for a later pass, whose LDS
+  // needs differ) runs with the set halved until it fits, down to one entry per thread: the set's
+  // size changes how many duplicates a chunk merges, not the result.  The pass's statistics
+  // report the set size it ran with.
+  while (scan_lds_bytes(p, mode, occ) > lds_budget && p.set_cap > c->lc.block) p.set_cap >>= 1;
   if (scan_lds_bytes(p, mode, occ) > lds_budget)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
                      (unsigned long long)scan_lds_bytes(p, mode, occ));
   const uint32_t block = c->lc.block;
   const uint32_t grid = (uint32_t)c->n_cu * wpc;
+  c->last.set_cap = p.set_cap;
   c->last.chunk_syms = c->lc.chunk_syms;
   c->last.block = block;
   c->last.grid = grid;

@@ -344,7 +344,7 @@ struct LaunchCfg {
   uint32_t grid_per_cu = 1;
   uint32_t set_cap = 8192;
   uint32_t filt_max_words = 16384;   // 64 KB of LDS
-  uint32_t map_log2 = 1;             // map slots >= kept << map_log2 (load <= 1/2)
+  uint32_t map_log2 = 2;             // map slots >= kept << map_log2 (load <= 1/4)
   uint32_t bloom_bits = 12;          // Bloom filter image: bits per retained key (within filt_max_words)
 };
 

@@ -51,6 +51,58 @@ def test_launch_shapes_same_result(shape):
     assert_tables_equal(got, exp, "shape %s" % (shape,))
 
 
+def test_shape_too_large_for_a_pass_runs_with_a_smaller_set():
+    """A launch shape whose LDS set does not fit some pass runs that pass with the set halved; the
+    set size in use is reported, and every table is the oracle's.  With 31744-symbol chunks and a
+    16384-entry set, pass 4 (k = 60,000 retained 3-grams: a 64 KB Bloom image in LDS) does not fit
+    even without the survivor rings, while passes 1 and 2 (direct-indexed) do."""
+    corpus = gen.workload(2, m=40)
+    ns, k = list(range(1, 5)), 60_000
+    exp, _ = oracle_tables(corpus, ns, k)
+    g = ig.Intergrams()
+    try:
+        g.set_launch(31744, 1024, 16384)
+        g.set_tables(filter_max_words=16384, filter_bits_per_key=12)
+        g.load(corpus)
+        got, caps = [], []
+        for n in ns:
+            g.pass_(n, k)
+            keys, counts = g.topk()
+            got.append((keys.copy(), counts.copy()))
+            caps.append(g.last_stats()["set_cap"])
+        say("LDS set in use per pass:", caps)
+        assert all(c in (1024, 2048, 4096, 8192, 16384) for c in caps), caps
+        assert caps[0] == 16384 and caps[3] < 16384, caps
+        assert_tables_equal(got, exp, "set fallback")
+        assert g.launch()["set_cap"] == 16384   # the launch shape itself is unchanged
+    finally:
+        g.close()
+
+
+def test_autotune_skips_shapes_that_need_a_smaller_set():
+    """At pass 4 with k = 60,000 (a 64 KB Bloom image), the 16384-symbol, 16384-entry candidate
+    fits only with a smaller set: it is reported unusable, and the chain is left as it was."""
+    corpus = gen.workload(2, m=40)
+    k = 60_000
+    exp, _ = oracle_tables(corpus, [1, 2, 3, 4], k)
+    g = ig.Intergrams()
+    try:
+        g.load(corpus)
+        for n in (1, 2, 3):
+            g.pass_(n, k)
+        rep = g.autotune(4, k)
+        assert rep["identical"]
+        assert g.table_info() == (3, len(exp[2][1]))
+        bad = [(c["chunk_syms"], c["block"], c["set_cap"]) for c in rep["candidates"] if c["pass_ms"] < 0]
+        say("autotune at pass 4, unusable shapes:", bad)
+        assert (16384, 1024, 16384) in bad
+        g.pass_(4, k)
+        keys, counts = g.topk()
+        assert np.array_equal(keys, exp[3][0]) and np.array_equal(counts, exp[3][1])
+    finally:
+        g.close()
+
+
 def test_autotune_is_deterministic_and_keeps_state():
     corpus = gen.workload(2, m=48)
     say("autotune on pass 5, workload 2 first 48 files")
