@@ -232,7 +232,7 @@ void ig_destroy(ig_ctx *c) {
   c->graphs.clear();
   DevBuf *bufs[] = {&c->data, &c->offs, &c->chunks_lpt, &c->chunks_file, &c->code, &c->sym_of_code, &c->qctr,
                     &c->status, &c->kdev, &c->zero, &c->cnt, &c->rec0, &c->nrec, &c->hist1, &c->g1, &c->scan_tmp, &c->base1, &c->bend, &c->bshift, &c->dscal, &c->l1, &c->l2, &c->hist2, &c->g2, &c->fin, &c->nsegs, &c->seg0, &c->tkey_lo, &c->tkey_hi, &c->tstate, &c->sel_cid, &c->sel_cnt, &c->sel_klo,
-                    &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist};
+                    &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist, &c->pmask};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
     DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.le_lo, &t.le_hi, &t.map, &t.filt, &t.qmap, &t.qflag};
@@ -346,11 +346,20 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   int mode = filtered ? MODE_FILTERED : ((uint64_t)n * b <= 26 ? MODE_DENSE : MODE_SPARSE);
   // The previous pass kept every (n-1)-gram over the alphabet (kept = sigma^(n-1)): every window
   // passes Algorithm 3's prefix test, so the pass is the unfiltered count of all n-grams, and it
-  // is direct-indexed when its keys fit (no prefix lookup per window).
+  // is direct-indexed when its keys fit (no prefix lookup per window).  When it kept at least
+  // half of them, the direct-indexed count of all n-grams is still cheaper than looking every
+  // window's prefix up: the grams whose prefix was not kept are then made ineligible before the
+  // selection (mask_prefix), which leaves the filtered pass's counts exactly.
+  bool mask_prefix = false;
   if (filtered && (uint64_t)n * b <= 26) {
-    uint64_t space = 1;
-    for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
-    if (space <= c->kept) mode = MODE_DENSE;
+    uint64_t space = 1;   // sigma^(n-1) <= 2^((n-1) b) <= 2^26
+    for (uint32_t j = 0; j + 1 < n; j++) space *= c->sigma;
+    if (space <= c->kept) {
+      mode = MODE_DENSE;
+    } else if (space <= 2 * c->kept) {
+      mode = MODE_DENSE;
+      mask_prefix = true;
+    }
   }
   const int kw = (uint64_t)n * b > 64 ? 2 : 1;
   const int count64 = occ && W >= 0xFFFFFFFFull ? 1 : 0;
@@ -530,6 +539,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     const uint64_t kmax = std::min<uint64_t>(kmax0, nc);
     int rc = select_reserve(c, nc, k_keep);
     if (rc) return rc;
+    if (mask_prefix && dev_reserve(c, c->pmask, ((1ull << ((n - 1) * b)) + 31) / 32 * 4)) return IG_ENOMEM;
     TableSet &nt = c->ts[c->nxt];
     rc = index_reserve(c, nt, n, kmax);
     if (rc) return rc;
@@ -587,7 +597,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       } else if (k == 2) {
         if (!occ) e = dedup_enqueue(dp, c->n_cu, s);
       } else {
-        e = select_enqueue(c, sp, k_keep, n * b, sel_count_bits);
+        if (mask_prefix)
+          e = prefix_mask_enqueue(c, reinterpret_cast<const uint64_t *>(c->T().lo.p), c->T().kept, (n - 1) * b, p.cnt,
+                                  count64, nc, b, reinterpret_cast<uint32_t *>(c->pmask.p), s);
+        if (e == hipSuccess) e = select_enqueue(c, sp, k_keep, n * b, sel_count_bits);
         if (e == hipSuccess) e = index_enqueue(c, nt, kmax, select_kept_ptr(c));
       }
       return e;
@@ -606,6 +619,7 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       }
       const uint64_t extra[] = {n, k_keep, kmax, nc, (uint64_t)mode, (uint64_t)kw, (uint64_t)occ, (uint64_t)count64,
                                 sel_count_bits, grid, block, c->rec_cap, c->tkey_slots, c->alloc_gen,
+                                (uint64_t)mask_prefix, mask_prefix ? c->T().kept : 0ull, (uint64_t)(uintptr_t)c->pmask.p,
                                 nt.map_mask, nt.filt_words, nt.filt_kind,
                                 (uint64_t)(uintptr_t)nt.lo.p, (uint64_t)(uintptr_t)nt.map.p, (uint64_t)(uintptr_t)nt.filt.p};
       std::string key(reinterpret_cast<const char *>(&p), sizeof p);

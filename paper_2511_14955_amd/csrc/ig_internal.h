@@ -388,6 +388,7 @@ struct ig_ctx {
   uint64_t rec_cap = 0;         // records the bucketed arrays hold (multiple of the tile)
   bool rec_floor = false;       // a caller set rec_cap: raise it only to the per-pass floor, not to the size guess
   ig::DevBuf sel_cid, sel_cnt, sel_klo, sel_khi, tie_a, tie_b, sort_tmp, hist, selstate, thist;
+  ig::DevBuf pmask;   // kept (n-1)-grams as bits, for a direct-indexed pass with part of the prefixes kept
 
   ig_pass_stats last{};
   hipEvent_t ev[5]{};
@@ -428,6 +429,9 @@ hipError_t launch_scan_feat(const ScanParams &p, int bits, int kw, uint32_t grid
 int select_reserve(ig_ctx *c, uint64_t nc, uint64_t k_keep);
 hipError_t select_enqueue(ig_ctx *c, const SelectParams &sp, uint64_t k_keep, uint32_t key_bits, uint32_t count_bits);
 const unsigned long long *select_kept_ptr(ig_ctx *c);
+// zero the counts of grams whose (n-1)-prefix the previous table did not keep (ig_select.hip)
+hipError_t prefix_mask_enqueue(ig_ctx *c, const uint64_t *prev_keys, uint64_t prev_kept, uint32_t prefix_bits, void *cnt,
+                               int c64, uint64_t nc, uint32_t b, uint32_t *bits, hipStream_t s);
 int select_read(ig_ctx *c, uint64_t *kept, uint64_t *distinct);
 // map + filter over a table set (sizes bounded by k_max; the length is read on the device)
 int index_reserve(ig_ctx *c, TableSet &t, uint32_t n, uint64_t k_max);

@@ -349,6 +349,46 @@ static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap) {
   return (uint32_t)g;
 }
 
+// A pass run as the direct-indexed count of every n-gram although the previous table kept only
+// part of the (n-1)-grams (Algorithm 3's prefix test then passes most windows): the grams whose
+// prefix was not kept are made ineligible (count 0) before the selection, which leaves exactly
+// the counts of the filtered pass.  bits: one bit per (n-1)-gram key, set for the kept ones.
+__global__ void k_prefix_bits(const uint64_t *keys, uint64_t kept, uint32_t *bits) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[i];
+    atomicOr(bits + (k >> 5), 1u << (k & 31));
+  }
+}
+__global__ void k_prefix_mask(void *cnt, int c64, uint64_t nc, uint32_t b, const uint32_t *bits) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t pre = i >> b;
+    if ((bits[pre >> 5] >> (pre & 31)) & 1u) continue;
+    if (c64) {
+      uint64_t *q = reinterpret_cast<uint64_t *>(cnt) + i;
+      if (*q) *q = 0;
+    } else {
+      uint32_t *q = reinterpret_cast<uint32_t *>(cnt) + i;
+      if (*q) *q = 0;
+    }
+  }
+}
+
+hipError_t prefix_mask_enqueue(ig_ctx *c, const uint64_t *prev_keys, uint64_t prev_kept, uint32_t prefix_bits, void *cnt,
+                               int c64, uint64_t nc, uint32_t b, uint32_t *bits, hipStream_t s) {
+  const uint64_t words = ((1ull << prefix_bits) + 31) / 32;
+  hipError_t e = launch_fill_u32(bits, words, 0, s);
+  if (e != hipSuccess) return e;
+  const uint32_t gmax = (uint32_t)c->n_cu * 8;
+  if (prev_kept) {
+    const uint32_t g = (uint32_t)std::min<uint64_t>(gmax, (prev_kept + 255) / 256);
+    hipLaunchKernelGGL(k_prefix_bits, dim3(g), dim3(256), 0, s, prev_keys, prev_kept, bits);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const uint32_t g = (uint32_t)std::min<uint64_t>(gmax, (nc + 255) / 256);
+  hipLaunchKernelGGL(k_prefix_mask, dim3(g ? g : 1), dim3(256), 0, s, cnt, c64, nc, b, (const uint32_t *)bits);
+  return hipGetLastError();
+}
+
 int select_reserve(ig_ctx *c, uint64_t nc, uint64_t k_keep) {
   const uint64_t K = k_keep < nc ? k_keep : nc;
   const uint64_t Kc = K ? K : 1;

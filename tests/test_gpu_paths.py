@@ -192,3 +192,28 @@ def test_set_overflow_bypass_and_dense_chain_pass(occ):
         assert_tables_equal(got, exp, "random bytes")
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("bits,occ", [(2, False), (2, True), (8, False), (8, True)])
+def test_direct_count_with_part_of_the_prefixes_kept(bits, occ):
+    """A pass whose previous table kept at least half (not all) of the (n-1)-grams over the
+    alphabet runs as the direct-indexed count of every n-gram, and the grams whose prefix was not
+    kept are dropped before the selection.  2-bit: k = 700 keeps 700 of the 1024 5-grams, so
+    pass 6 takes this form; bytes over 40 symbols: k = 1000 keeps 1000 of the 1600 2-grams, so
+    pass 3 does.  Every table equals the oracle's."""
+    rng = np.random.default_rng(3030 + bits + occ)
+    if bits == 2:
+        files = [rng.integers(0, 4, size=int(rng.integers(100_000, 300_000)), dtype=np.uint8) for _ in range(6)]
+        ns, k = list(range(1, 8)), 700
+    else:
+        files = [rng.integers(0, 40, size=int(rng.integers(100_000, 300_000)), dtype=np.uint8) for _ in range(6)]
+        ns, k = list(range(1, 5)), 1000
+    corpus = gen.from_files(files, bits)
+    say("direct-indexed pass with part of the prefixes kept: %d-bit, n=1..%d, k=%d, %s"
+        % (bits, ns[-1], k, "Eq. 1" if occ else "Eq. 2"))
+    exp, _ = oracle_tables(corpus, ns, k, occ)
+    got, g = gpu_tables(corpus, ns, k, occ)
+    try:
+        assert_tables_equal(got, exp, "part of the prefixes kept")
+    finally:
+        g.close()
