@@ -137,6 +137,7 @@ def cpu_baseline(n, k_keep, sample_files, threads, target_s=10.0):
     corpus, dt = timed(sample_files)
     if dt < target_s / 2 and sample_files < m_all:
         sample_files = min(m_all, max(sample_files + 1, int(sample_files * target_s / max(dt, 1e-3))))
+        log("cpu baseline: %d files took %.2f s; timing %d files" % (corpus.m, dt, sample_files))
         corpus, dt = timed(sample_files)
     # one thread on the tiny plain run (64 files x 64 KiB, n = 1..4, k = 1000)
     tiny = gen.workload(1)
