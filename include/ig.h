@@ -229,7 +229,8 @@ const char *ig_last_error(const ig_ctx *ctx);
  * launch shape first, then, with the best one, the table sizes of
  * ig_set_tables (map_slots_log2 1 or 2, filter_max_words 8192 or 16384),
  * which apply to the current table's index, and last two workgroups per CU
- * (Bloom image in L2, 4096-entry LDS set, chunks of 12288 or 16384 symbols).  With the
+ * (Bloom image in L2, 4096-entry LDS set, chunks of 12288, 16384 or the winner's symbols,
+ * 512- or 1024-thread workgroups).  With the
  * environment variable IG_TUNE_CACHE naming a file, results are read from and
  * appended to it, keyed by device, corpus shape and (n, k_keep).
  * --------------------------------------------------------------------------- */

@@ -227,17 +227,22 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
         win_idx = nrep - 1;
       }
     }
-  // stage 3: two workgroups per CU (twice the wavefronts to hide probe latency), which needs a
-  // workgroup's LDS to fit half a CU: the Bloom image in L2 (an LDS cap of 1024 words sends it
-  // there) and a shorter chunk with a smaller LDS set
-  for (uint32_t cs : {12288u, 16384u})
-    for (uint32_t ml : {1u, 2u}) {
+  // stage 3: two workgroups per CU, which needs a workgroup's LDS to fit half a CU: the Bloom
+  // image in L2 (an LDS cap of 1024 words sends it there) and a smaller LDS set, with shorter
+  // chunks or the winner's, and 512- or 1024-thread workgroups (512 threads give each thread a
+  // run twice as long: passes that read the Bloom image in L2 for every window run faster so)
+  const uint32_t win_cs = win.chunk_syms, win_ml = win.map_log2;
+  const uint32_t s3_chunks[3] = {12288u, 16384u, win_cs};
+  const int n3 = (win_cs == 12288u || win_cs == 16384u) ? 2 : 3;
+  for (int ci = 0; ci < n3; ci++)
+    for (uint32_t bl : {512u, 1024u}) {
+      const uint32_t cs = s3_chunks[ci];
       LaunchCfg lc = win;
       lc.chunk_syms = cs;
-      lc.block = 1024;
+      lc.block = bl;
       lc.set_cap = 4096;
       lc.grid_per_cu = 2;
-      lc.map_log2 = ml;
+      lc.map_log2 = win_ml;
       lc.filt_max_words = 1024;
       const double ms = trial(lc);
       if (ms <= -2.0) return restore((int)(ms + 2.0), nullptr);
