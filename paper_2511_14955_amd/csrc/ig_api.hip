@@ -413,7 +413,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // level-1 histogram: a filtered pass knows its bucket count now (its candidate space is fixed);
   // the other passes assume the largest (256 buckets per wavefront)
   p.hist_words = occ ? 0u : (c->lc.block / 64) * (mode == MODE_FILTERED ? dedup_shape(nc, c->m).nb1 : 256u);
-  p.qbytes = (mode == MODE_FILTERED && kw == 1) ? (c->lc.block / 64) * SCAN_QCAP * 10u : 0u;   // 8 B key + 2 B step
+  // survivor rings (8 or 16 B of window per entry + a 2 B step): keys of at most 64 bits, and
+  // byte Eq. 2 passes with keys of up to 128 (the scan kernel's compacted forms)
+  const bool rings = mode == MODE_FILTERED && (kw == 1 || (b == 8 && !occ));
+  p.qbytes = rings ? (c->lc.block / 64) * SCAN_QCAP * (8u * kw + 2u) : 0u;
   // LDS a workgroup may take: all of a CU's (less static use and slack) with one workgroup per
   // CU, half of it with two.  Two per CU is a request: a pass whose LDS does not fit half a CU
   // (with the survivor rings, when it would have them) runs one per CU.

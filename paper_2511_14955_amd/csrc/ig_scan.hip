@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
   uint64_t *s_q = reinterpret_cast<uint64_t *>(s_code + 256);
   // and, after the keys, 16 bits per ring entry: the next displacement to probe (the quotient
   // map's displacement field has at most 16 bits)
-  uint16_t *s_qd = reinterpret_cast<uint16_t *>(s_q + (size_t)(blockDim.x >> 6) * SCAN_QCAP);
+  uint16_t *s_qd = reinterpret_cast<uint16_t *>(s_q + (size_t)(blockDim.x >> 6) * SCAN_QCAP * KW);
   uint32_t *s_h1w = reinterpret_cast<uint32_t *>(s_code + 256 + p.qbytes);
   __shared__ uint32_t s_chunk, s_next;
 
@@ -313,7 +313,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         // words (v_alignbit); the prefix is a mask of them, the last symbol a bit field.
         constexpr int RBC = 4;
         constexpr uint32_t SPD = 32 / B;   // symbols per stage word
-        uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP;
+        // ring entries: the window's first 64 bits (KW 2: its first 128, as two words)
+        uint64_t *q = s_q + (tid >> 6) * SCAN_QCAP * KW;
         uint16_t *qd = s_qd + (tid >> 6) * SCAN_QCAP;
         const uint32_t rmask = p.rank_bits >= 32 ? 0xFFFFFFFFu : ((1u << p.rank_bits) - 1);
         const uint64_t rmask64 = rmask;
@@ -322,6 +323,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         const uint32_t pm_lo = pb >= 32 ? 0xFFFFFFFFu : ((1u << pb) - 1);
         const uint32_t pm_hi = pb <= 32 ? 0u : (pb >= 64 ? 0xFFFFFFFFu : ((1u << (pb - 32)) - 1));
         const uint64_t pmask = ((uint64_t)pm_hi << 32) | pm_lo;
+        // KW 2: the prefix's bits in the window's second 64 (pb >= 64 there)
+        const uint64_t pmask2 = KW == 2 ? (pb >= 128 ? ~0ull : ((1ull << (pb - 64)) - 1)) : 0ull;
         // Exact rank of each queued key's prefix.  With the quotient map one 8-byte slot read
         // decides (home and stored bits give back the key); otherwise the fingerprinted map and
         // the table's keys are probed.  An empty slot ends either probe.
@@ -335,14 +338,19 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         auto drain = [&](uint32_t cnt) {
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           bool again = false;
-          uint64_t key = 0;
+          uint64_t key = 0, key2 = 0;   // (key2: KW 2's second word)
           uint32_t dnext = 0;
           uint32_t newcid = LDS_EMPTY;   // Eq. 2: a candidate new to the chunk, recorded below
           if (lane < cnt) {
-            key = q[(head + lane) & (SCAN_QCAP - 1)];
+            key = q[((head + lane) & (SCAN_QCAP - 1)) * KW];
+            if (KW == 2) key2 = q[((head + lane) & (SCAN_QCAP - 1)) * KW + 1];
             const uint32_t d = qd[(head + lane) & (SCAN_QCAP - 1)];
             const uint64_t plo = key & pmask;
-            const uint32_t code = FEAT ? 0u : s_code[(uint32_t)(key >> pb) & ((1u << B) - 1)];
+            const uint64_t phi = key2 & pmask2;
+            // the window's last symbol sits right above its prefix (counting passes: pb < 64 for
+            // KW 1, 64 <= pb < 128 for KW 2)
+            const uint32_t code =
+                FEAT ? 0u : s_code[(KW == 2 ? (uint32_t)(key2 >> (pb - 64)) : (uint32_t)(key >> pb)) & ((1u << B) - 1)];
             uint32_t cid = LDS_EMPTY;   // not found
             if (useq) {
               // one 16-byte read covers displacements d and d+1 (the slot past the last mirrors
@@ -361,14 +369,15 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               again = !(m0 || m1) && (e0 & rmask64) != 0 && (e1 & rmask64) != 0 && d + 2 <= dmax;
               dnext = d + 2;
             } else {
-              const uint64_t h = hash_key(plo, 0);
+              // the fingerprinted map, confirmed against the table's key (KW 2: both words)
+              const uint64_t h = hash_key(plo, phi);
               const uint32_t fp = map_fp(h, p.rank_bits);
               uint64_t slot = h & p.mmask;
               uint32_t v = p.map[slot];
               while (v != 0) {
                 if (p.rank_bits >= 32 || (v >> p.rank_bits) == fp) {
                   const uint32_t r = (v & rmask) - 1;
-                  if (p.tkeys_lo[r] == plo) {
+                  if (p.tkeys_lo[r] == plo && (KW == 1 || p.tkeys_hi[r] == phi)) {
                     cid = r * p.sigma + code;
                     break;
                   }
@@ -397,9 +406,10 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           }
           // requeue behind the live entries: at most 63 + cnt <= 127 entries are live afterwards
           const uint64_t m = __ballot(again);
-          if (again) {
+          if (again) {   // (quotient map only: keys of at most 64 bits)
             const uint32_t at = (tail + (uint32_t)__popcll(m & lanes_below)) & (SCAN_QCAP - 1);
-            q[at] = key;
+            q[at * KW] = key;
+            if (KW == 2) q[at * KW + 1] = key2;
             qd[at] = (uint16_t)dnext;
           }
           tail += (uint32_t)__popcll(m);
@@ -434,8 +444,13 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
           constexpr int FK = decltype(kind)::value;
           uint32_t j = p0 / SPD;
           uint32_t D0 = rd(j), D1 = rd(j + 1);
+          // KW 2 (byte windows of up to 16 symbols): five words hold a window at any of the four
+          // byte offsets of the first; D2c and D3c carry the third and fourth across words
+          uint32_t D2c = KW == 2 ? rd(j + 2) : 0u, D3c = KW == 2 ? rd(j + 3) : 0u;
           for (uint32_t it = 0; it < run; it += SPD, j++) {
-            const uint32_t D2 = rd(j + 2);
+            const uint32_t D2 = KW == 2 ? D2c : rd(j + 2);
+            const uint32_t D3 = D3c;
+            const uint32_t D4 = KW == 2 ? rd(j + 4) : 0u;
 #pragma unroll 1
             for (uint32_t e0 = 0; e0 < SPD; e0 += RBC) {
               // the RBC windows at run positions it + e0 + u: keys, filter positions, then the
@@ -447,7 +462,18 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
                 const uint32_t sh = B * (e0 + u);
                 const uint32_t pl = __builtin_amdgcn_alignbit(D1, D0, sh) & pm_lo;
                 const uint32_t ph = __builtin_amdgcn_alignbit(D2, D1, sh) & pm_hi;
-                if constexpr (FK == FILT_BLOOM || FK == FILT_GBLOOM) {
+                if constexpr (KW == 2) {
+                  // the prefix's first 64 bits are (ph, pl) unmasked (pb >= 64); its rest is the
+                  // next 64 masked to pb - 64 bits.  (A direct bitmap never serves such keys.)
+                  const uint64_t phi = (((uint64_t)__builtin_amdgcn_alignbit(D4, D3, sh) << 32) |
+                                        __builtin_amdgcn_alignbit(D3, D2, sh)) & pmask2;
+                  if constexpr (FK == FILT_BLOOM || FK == FILT_GBLOOM)
+                    bloom_pos(fold_le(((uint64_t)ph << 32) | pl, phi), p.filt_words, &widx[u], &bm[u]);
+                  else if constexpr (FK == FILT_DIRECT) {
+                    widx[u] = 0;
+                    bm[u] = 0;
+                  }
+                } else if constexpr (FK == FILT_BLOOM || FK == FILT_GBLOOM) {
                   bloom_pos(pl ^ ((ph >> 13) | (ph << 19)), p.filt_words, &widx[u], &bm[u]);
                 } else if constexpr (FK == FILT_DIRECT) {
                   widx[u] = (pl >> 5) & fmask;
@@ -476,7 +502,10 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
                       __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                   const uint32_t at = (tail + below) & (SCAN_QCAP - 1);
                   const uint32_t sh = B * (e0 + u);
-                  q[at] = ((uint64_t)__builtin_amdgcn_alignbit(D2, D1, sh) << 32) | __builtin_amdgcn_alignbit(D1, D0, sh);
+                  q[at * KW] = ((uint64_t)__builtin_amdgcn_alignbit(D2, D1, sh) << 32) | __builtin_amdgcn_alignbit(D1, D0, sh);
+                  if (KW == 2)
+                    q[at * KW + 1] =
+                        ((uint64_t)__builtin_amdgcn_alignbit(D4, D3, sh) << 32) | __builtin_amdgcn_alignbit(D3, D2, sh);
                   qd[at] = 0;
                 }
                 tail += (uint32_t)__popcll(m);
@@ -486,6 +515,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
             }
             D0 = D1;
             D1 = D2;
+            D2c = D3;
+            D3c = D4;
           }
         };
         if (p.filt_kind == FILT_BLOOM) windows(std::integral_constant<int, FILT_BLOOM>{});
@@ -696,7 +727,9 @@ size_t scan_lds_bytes(const ScanParams &p, int mode, int occ, int feat) {
 template <int B, int KW, int MODE, int OCC, typename CT, int FEAT = 0>
 static hipError_t launch_t(const ScanParams &p, uint32_t grid, uint32_t block, hipStream_t s) {
   const size_t lds = scan_lds_bytes(p, MODE, OCC, FEAT);
-  constexpr int can_cmp = (MODE == MODE_FILTERED && KW == 1) ? 1 : 0;
+  // survivor rings: filtered passes with keys of at most 64 bits, and Eq. 2 passes over bytes with
+  // keys of up to 128 (their windows take five stage words); featurize keeps 128-bit keys in place
+  constexpr int can_cmp = (MODE == MODE_FILTERED && (KW == 1 || (B == 8 && !OCC && !FEAT))) ? 1 : 0;
   auto fn0 = k_scan<B, KW, MODE, OCC, CT, 0, FEAT>;
   auto fn1 = k_scan<B, KW, MODE, OCC, CT, can_cmp, FEAT>;
   if (grid == 0) {   // preparation call: allow the whole LDS of a CU (never issued during a capture)
