@@ -235,7 +235,7 @@ void ig_destroy(ig_ctx *c) {
                     &c->sel_khi, &c->tie_a, &c->tie_b, &c->sort_tmp, &c->hist, &c->selstate, &c->thist, &c->pmask};
   for (DevBuf *b : bufs) dev_release(c, *b);
   for (TableSet &t : c->ts) {
-    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.le_lo, &t.le_hi, &t.map, &t.filt, &t.qmap, &t.qflag};
+    DevBuf *tb[] = {&t.lo, &t.hi, &t.cnt, &t.le_lo, &t.le_hi, &t.map, &t.filt, &t.qmap, &t.qflag, &t.qmap2};
     for (DevBuf *b : tb) dev_release(c, *b);
   }
   for (auto &e : c->ev)
@@ -406,6 +406,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
       p.qmap = reinterpret_cast<const uint64_t *>(t.qmap.p);
       p.qflag = reinterpret_cast<const uint32_t *>(t.qflag.p);
       p.qs = t.qs;
+    } else if (t.has_qmap2) {
+      p.qmap2 = reinterpret_cast<const uint64_t *>(t.qmap2.p);
+      p.qflag = reinterpret_cast<const uint32_t *>(t.qflag.p);
+      p.qs2 = t.qs2;
     }
   }
   p.set_cap = c->lc.set_cap;

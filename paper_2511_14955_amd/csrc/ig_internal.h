@@ -102,6 +102,39 @@ __host__ __device__ __forceinline__ uint64_t qmix(uint64_t x, uint32_t w) {
   x = (x * 0xFF51AFD7ED558CCDull) & m;
   return x ^ (x >> s);
 }
+// Quotient map with 16-byte slots, for tables whose 8-byte slots cannot hold remainder,
+// displacement and rank: prefixes of more than 64 bits (up to 128), or of up to 64 bits with many
+// keys.  qmix2 is a bijection of w-bit values, lo the first 64 bits and hi the other w - 64:
+//   w <= 64: qmix of lo (as above);
+//   w > 64:  a = mix64(lo); b = hi xor (a times an odd constant), cut to w - 64 bits;
+//            a' = mix64(a xor (b times an odd constant)).
+// Each step is invertible (mix64, the finalizer above, is xor-shifts and odd multiplies; an xor of
+// a function of the other half is undone by the same xor), so (a', b) gives back the key.  The home slot is the
+// top sbits of the mix (of a' for w > 64) and the remainder the rest of it, (a' below the home,
+// then b) for w > 64.  A slot holds rank+1 in its low rbits, the displacement from home in the
+// next dbits, and the remainder above them: one 16-byte read identifies its key.
+// home slot and remainder (rl: its low 64 bits, rh: the rest) of a w-bit key in 2^sbits slots
+__host__ __device__ __forceinline__ void qmix2(uint64_t lo, uint64_t hi, uint32_t w, uint32_t sbits, uint64_t *home,
+                                               uint64_t *rl, uint64_t *rh) {
+  if (w <= 64) {
+    const uint64_t x = qmix(lo, w);
+    const uint32_t qb = w - sbits;   // 1 <= qb <= 54 (sbits >= 10, and w > sbits for such tables)
+    *home = x >> qb;
+    *rl = x & ((1ull << qb) - 1);
+    *rh = 0;
+    return;
+  }
+  const uint32_t bw = w - 64;
+  const uint64_t bm = bw >= 64 ? ~0ull : ((1ull << bw) - 1);
+  const uint64_t a = mix64(lo);
+  const uint64_t b = (hi ^ (a * 0x9E3779B97F4A7C15ull)) & bm;
+  const uint64_t a2 = mix64(a ^ (b * 0xC2B2AE3D27D4EB4Full));
+  const uint32_t lb = 64 - sbits;   // bits of a' below the home (10 <= sbits <= 40)
+  *home = a2 >> lb;
+  *rl = (a2 & ((1ull << lb) - 1)) | (b << lb);
+  *rh = b >> (64 - lb);
+}
+
 // Blocked Bloom filter position of a key's 32-bit fold (filter of `words` 32-bit words, a power
 // of two): one 32 x 32 -> 64-bit multiply; the word and the three bits come from the product's
 // high word.  (Folding only adds collisions of about k / 2^32 per query; a filter has no false
@@ -236,9 +269,10 @@ struct ScanParams {
   uint32_t rank_bits;            // low bits of a slot holding rank+1
   const uint64_t *tkeys_lo, *tkeys_hi;   // previous table's keys (stream forms), in rank order
   const uint64_t *qmap;          // quotient map of the previous table (null: none)
+  const uint64_t *qmap2;         // its 16-byte-slot quotient map (null: none; survivor-ring drains only)
   const uint32_t *qflag;         // non-zero: a key of that table did not fit its displacement field (lookups
                                  // then use the fingerprinted map and the table's keys)
-  QMapShape qs;
+  QMapShape qs, qs2;
   // large unfiltered passes: key table
   uint64_t *tkey_lo, *tkey_hi;
   uint32_t *tstate;
@@ -331,11 +365,12 @@ struct TableSet {
   DevBuf le_lo, le_hi;            // the keys' stream forms, in rank order (probes confirm against them)
   DevBuf map, filt;               // map: 32-bit fingerprinted slots (rank+1 in the low rank_bits)
   DevBuf qmap, qflag;             // quotient map (keys of at most 64 bits) and its overflow flag
+  DevBuf qmap2;                   // the 16-byte-slot quotient map, where 8-byte slots do not fit
   uint64_t kept = 0, map_mask = 0;
   uint32_t rank_bits = 32;
   uint32_t n = 0, filt_words = 0, filt_kind = 0;
-  bool has_qmap = false;
-  QMapShape qs{};
+  bool has_qmap = false, has_qmap2 = false;
+  QMapShape qs{}, qs2{};
 };
 
 struct LaunchCfg {

@@ -329,6 +329,13 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
         // decides (home and stored bits give back the key); otherwise the fingerprinted map and
         // the table's keys are probed.  An empty slot ends either probe.
         const bool useq = p.qmap != nullptr && *p.qflag == 0u;
+        // the 16-byte-slot quotient map (tables whose 8-byte slots do not fit: the host builds it
+        // for prefixes of more than 64 bits, or of 64 with many keys, whose windows take this
+        // kernel's 128-bit form): the same probe, with 32-byte reads of two slots
+        const bool useq2 = KW == 2 && !useq && p.qmap2 != nullptr && *p.qflag == 0u;
+        const uint64_t dmax2 = (1ull << p.qs2.dbits) - 1;
+        const uint32_t sh2 = p.qs2.rbits + p.qs2.dbits;
+        const uint64_t rmask2 = p.qs2.rbits >= 64 ? ~0ull : ((1ull << p.qs2.rbits) - 1);
         const uint64_t dmax = (1ull << p.qs.dbits) - 1;
         const uint32_t rsh = p.qs.rbits + p.qs.dbits;
         const uint64_t qmaskq = p.qs.qbits ? ((1ull << p.qs.qbits) - 1) : 0ull;
@@ -367,6 +374,22 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
               const bool m1 = (e1 & rmask64) != 0 && (e1 & ~rmask64) == want1 && d + 1 <= dmax;
               if (m0 || m1) cid = (((uint32_t)(m0 ? e0 : e1) & rmask) - 1) * p.sigma + code;
               again = !(m0 || m1) && (e0 & rmask64) != 0 && (e1 & rmask64) != 0 && d + 2 <= dmax;
+              dnext = d + 2;
+            } else if (KW == 2 && useq2) {
+              // slots d and d+1 (the slot past the last mirrors slot 0) in one 32-byte read; a slot
+              // holds the key whose remainder and displacement are exactly the wanted ones
+              uint64_t home, rl, rh;
+              qmix2(plo, phi, p.qs2.w, p.qs2.sbits, &home, &rl, &rh);
+              const uint64_t slot = (home + d) & p.mmask;
+              typedef unsigned long long u64x4_t __attribute__((ext_vector_type(4), aligned(16)));
+              const u64x4_t e4 = *reinterpret_cast<const u64x4_t *>(p.qmap2 + 2 * slot);
+              const uint64_t wlo = (rl << sh2) | ((uint64_t)d << p.qs2.rbits);
+              const uint64_t whi = (rl >> (64 - sh2)) | (rh << sh2);
+              const bool m0 = (e4.x & rmask2) != 0 && (e4.x & ~rmask2) == wlo && e4.y == whi;
+              const bool m1 = (e4.z & rmask2) != 0 && (e4.z & ~rmask2) == wlo + (1ull << p.qs2.rbits) && e4.w == whi &&
+                              d + 1 <= dmax2;
+              if (m0 || m1) cid = (((uint32_t)(m0 ? e4.x : e4.z) & rmask) - 1) * p.sigma + code;
+              again = !(m0 || m1) && (e4.x & rmask2) != 0 && (e4.z & rmask2) != 0 && d + 2 <= dmax2;
               dnext = d + 2;
             } else {
               // the fingerprinted map, confirmed against the table's key (KW 2: both words)

@@ -78,6 +78,39 @@ __global__ void k_qmap_mirror(unsigned long long *qmap, uint64_t mmask) {
   if (threadIdx.x == 0) qmap[mmask + 1] = qmap[0];
 }
 
+// The same for the 16-byte-slot quotient map (keys of up to 128 bits, stream forms lo and hi): a
+// slot is claimed by a compare-and-swap of its first word (rank+1, displacement and the
+// remainder's low bits: never zero), and its second word (the rest of the remainder) is stored
+// after; the scan reads the map only once the build has finished.
+__global__ void k_qmap2_insert(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint64_t r0,
+                               uint64_t r1, unsigned long long *qmap2, uint32_t *qflag, uint64_t mmask, QMapShape qs) {
+  const uint64_t kept = *kept_p < r1 ? *kept_p : r1;
+  const uint64_t dmax = (1ull << qs.dbits) - 1;
+  const uint32_t sh = qs.rbits + qs.dbits;
+  for (uint64_t i = r0 + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < kept; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t home, rl, rh;
+    qmix2(tlo[i], qs.w > 64 ? thi[i] : 0ull, qs.w, qs.sbits, &home, &rl, &rh);
+    const uint64_t w1 = (rl >> (64 - sh)) | (rh << sh);
+    uint64_t slot = home & mmask;
+    for (uint64_t d = 0;; d++) {
+      if (d > dmax) {
+        atomicOr(qflag, 1u);
+        break;
+      }
+      const uint64_t w0 = (rl << sh) | (d << qs.rbits) | (i + 1);
+      if (atomicCAS(qmap2 + 2 * slot, 0ull, (unsigned long long)w0) == 0ull) {
+        qmap2[2 * slot + 1] = w1;
+        break;
+      }
+      slot = (slot + 1) & mmask;
+    }
+  }
+}
+
+__global__ void k_qmap2_mirror(unsigned long long *qmap2, uint64_t mmask) {
+  if (threadIdx.x < 2) qmap2[2 * (mmask + 1) + threadIdx.x] = qmap2[threadIdx.x];
+}
+
 __global__ void k_filter_build(const uint64_t *tlo, const uint64_t *thi, const unsigned long long *kept_p, uint32_t *filt,
                                uint32_t words, uint32_t kind) {
   const uint64_t kept = *kept_p;
@@ -120,6 +153,7 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
       dev_reserve(c, ts.le_lo, std::max<uint64_t>(k_max, 1) * 8) || dev_reserve(c, ts.le_hi, std::max<uint64_t>(k_max, 1) * 8))
     return IG_ENOMEM;
   ts.has_qmap = false;
+  ts.has_qmap2 = false;
   if (nbits <= 64) {
     QMapShape qs{};
     qs.w = nbits;
@@ -133,6 +167,23 @@ int index_reserve(ig_ctx *c, TableSet &ts, uint32_t n, uint64_t k_max) {
       if (dev_reserve(c, ts.qmap, (cap + 1) * 8) || dev_reserve(c, ts.qflag, 64)) return IG_ENOMEM;
       ts.qs = qs;
       ts.has_qmap = true;
+    }
+  }
+  if (!ts.has_qmap && nbits <= 128 && nbits + c->cfg.symbol_bits > 64) {
+    // 16-byte slots: 128 bits hold the remainder (nbits - sbits), rank+1 and the displacement.
+    // (Only for a table whose next pass has windows of more than 64 bits: the scan's 128-bit form
+    // is the one that reads it.)
+    QMapShape qs{};
+    qs.w = nbits;
+    while ((1ull << qs.sbits) < cap) qs.sbits++;
+    qs.qbits = nbits > qs.sbits ? nbits - qs.sbits : 0;
+    qs.rbits = rb;
+    const int room = 128 - (int)qs.qbits - (int)qs.rbits;
+    if (nbits > qs.sbits && room >= 6) {
+      qs.dbits = room < 16 ? (uint32_t)room : 16u;
+      if (dev_reserve(c, ts.qmap2, (cap + 1) * 16) || dev_reserve(c, ts.qflag, 64)) return IG_ENOMEM;
+      ts.qs2 = qs;
+      ts.has_qmap2 = true;
     }
   }
   ts.n = n;   // (the stream forms are computed for this gram length)
@@ -173,6 +224,23 @@ hipError_t index_enqueue(ig_ctx *c, TableSet &ts, uint64_t k_max, const unsigned
       r0 = r1;
     }
     hipLaunchKernelGGL(k_qmap_mirror, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(ts.qmap.p),
+                       ts.map_mask);
+  }
+  if (ts.has_qmap2) {
+    if ((e = hipGetLastError()) == hipSuccess)
+      e = launch_fill_u64(reinterpret_cast<uint64_t *>(ts.qmap2.p), 2 * (ts.map_mask + 2), 0, s);
+    if (e == hipSuccess) e = launch_fill_u32(reinterpret_cast<uint32_t *>(ts.qflag.p), 1, 0, s);
+    if (e != hipSuccess) return e;
+    uint64_t r0 = 0;
+    for (uint64_t r1 = 256; r0 < k_max; r1 = r1 < (1ull << 14) ? r1 * 4 : k_max) {
+      uint64_t gb = (r1 - r0 + 255) / 256;
+      if (gb > 4096) gb = 4096;
+      hipLaunchKernelGGL(k_qmap2_insert, dim3((uint32_t)gb), dim3(256), 0, s, llo, lhi, kept_dev, r0, r1,
+                         reinterpret_cast<unsigned long long *>(ts.qmap2.p), reinterpret_cast<uint32_t *>(ts.qflag.p),
+                         ts.map_mask, ts.qs2);
+      r0 = r1;
+    }
+    hipLaunchKernelGGL(k_qmap2_mirror, dim3(1), dim3(64), 0, s, reinterpret_cast<unsigned long long *>(ts.qmap2.p),
                        ts.map_mask);
   }
   return hipGetLastError();
