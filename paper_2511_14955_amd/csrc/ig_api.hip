@@ -428,11 +428,10 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   uint32_t wpc = c->lc.grid_per_cu > 1 ? 2u : 1u;
   if (wpc == 2 && scan_lds_bytes(p, mode, occ) > lds_two) wpc = 1;
   const size_t lds_budget = wpc == 2 ? lds_two : lds_one;
-  // without LDS for the survivor rings the scan resolves survivors in place; so it does when
-  // the previous table holds every (n-1)-gram over the alphabet (every window survives)
-  if (p.qbytes && scan_lds_bytes(p, mode, occ) > lds_budget) p.qbytes = 0;
+  // the survivor rings need thread runs of whole stage words, at most 64 windows long; without
+  // them the scan resolves survivors in place, as it also does when the previous table holds
+  // every (n-1)-gram over the alphabet (every window survives)
   if (p.qbytes) {
-    // the compacted scan's thread runs are whole stage words and at most 64 windows long
     const uint64_t spd = 32 / b, span_max = c->lc.chunk_syms + 128 / b - 1;
     if (spd * ((span_max + spd * c->lc.block - 1) / (spd * c->lc.block)) > 64) p.qbytes = 0;
   }
@@ -441,10 +440,14 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
     for (uint32_t j = 0; j + 1 < n && space <= c->kept; j++) space *= c->sigma;
     if (space <= c->kept) p.qbytes = 0;
   }
-  // A shape whose LDS set does not fit this pass (say a shape tuned for a later pass, whose LDS
-  // needs differ) runs with the set halved until it fits, down to one entry per thread: the set's
-  // size changes how many duplicates a chunk merges, not the result.  The pass's statistics
-  // report the set size it ran with.
+  // A shape whose LDS does not fit this pass (say a shape tuned for a later pass, whose filter
+  // image, rings and histograms differ) keeps the rings first: the LDS set is halved, down to 4096
+  // entries, while they do not fit (the rings take the probes' divergence out; the set's size only
+  // changes how many duplicates a chunk merges, not the result); then the rings go; then the set
+  // is halved further, down to one entry per thread.  The pass's statistics report the set size.
+  const uint32_t set_floor = std::min<uint32_t>(p.set_cap, std::max<uint32_t>(4096u, c->lc.block));
+  while (p.qbytes && scan_lds_bytes(p, mode, occ) > lds_budget && p.set_cap > set_floor) p.set_cap >>= 1;
+  if (p.qbytes && scan_lds_bytes(p, mode, occ) > lds_budget) p.qbytes = 0;
   while (scan_lds_bytes(p, mode, occ) > lds_budget && p.set_cap > c->lc.block) p.set_cap >>= 1;
   if (scan_lds_bytes(p, mode, occ) > lds_budget)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
