@@ -123,7 +123,7 @@ def from_files(files, symbol_bits=8, name="custom"):
         data = np.concatenate(arrs) if arrs and offs[-1] else np.zeros(0, np.uint8)
         return Corpus(np.ascontiguousarray(data, np.uint8), offs, 8, name)
     if symbol_bits == 2:
-        data, offs = pack2([list(f) for f in files])
+        data, offs = pack2([f if isinstance(f, np.ndarray) else list(f) for f in files])
         return Corpus(data, offs, 2, name)
     raise ValueError("symbol_bits must be 8 or 2")
 

@@ -725,6 +725,8 @@ __global__ void __launch_bounds__(1024) k_scan(ScanParams p) {
       if (PF) {
         c0 = cn;
         c1 = claim;
+      } else if (p.persistent == 2) {   // strided (no queue counter is passed in this form)
+        c0 = ci + gridDim.x;
       } else if (p.persistent) {
         c0 = atomicAdd(p.qctr, 1u);
       }

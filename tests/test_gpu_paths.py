@@ -1,7 +1,8 @@
 """Kernel paths that only some shapes reach, each against the CPU oracle or a closed form.
 
-- Featurize with 128-bit keys (text, n = 10 > 8 byte symbols): ig_featurize, the loaded
-  corpus, and serving (featurize and count requests).
+- Featurize with 128-bit keys (bytes at n = 10, 2-bit symbols at n = 36): the featurizing
+  scan's in-place form, with more chunks than workgroups; ig_featurize, the loaded corpus, and
+  serving (featurize and count requests).
 - Featurize with a table too large for the per-workgroup rank bitmap in LDS (more than about
   590K kept grams): the rank bits then go straight to the sequence's bitmap in HBM.
 - Eq. 1 with 64-bit device counters (more than 2^32 windows), checked against closed forms,
@@ -89,6 +90,43 @@ def test_featurize_128bit_keys():
         more = gen.workload(3, m=90)
         q = gen.from_files([more.file(i) for i in range(60, 90)] + [b"", b"short", more.file(3)])
         _check_all_featurize_forms(g, o, corpus, q, "128-bit")
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("bits,n", [(8, 10), (2, 36)])
+def test_featurize_128bit_keys_in_place(bits, n):
+    """A fresh pass at n = 10 bytes (80-bit keys) or n = 36 two-bit symbols (72 bits), then the
+    featurizing scan against that table.  Its 128-bit form looks every window up in place (no
+    survivor rings), and the loaded corpus has more chunks than the grid has workgroups, so
+    each workgroup goes on to the chunk one grid further.  The files are overlapping slices of
+    one random sequence, so that long grams recur across files."""
+    rng = np.random.default_rng(5150 + bits)
+    glen = 3_000_000 if bits == 8 else 12_000_000
+    seq = rng.integers(0, 1 << bits, size=glen, dtype=np.uint8)
+
+    def piece(lo, hi):
+        ln = int(rng.integers(lo, hi))
+        a = int(rng.integers(0, glen - ln))
+        return seq[a:a + ln]
+
+    scale = 1 if bits == 8 else 2
+    files = [piece(200_000 * scale, 1_000_000 * scale) for _ in range(12)]
+    corpus = gen.from_files(files, bits)
+    k = 50_000
+    say("featurize, %d-bit keys in place: %d-bit symbols, fresh pass n=%d, k=%d, %d symbols"
+        % (n * bits, bits, n, k, int(corpus.offsets[-1])))
+    exp, o = oracle_tables(corpus, [n], k)
+    got, g = gpu_tables(corpus, [n], k)
+    try:
+        assert_tables_equal(got, exp, "fresh n=%d" % n)
+        assert int(got[0][0][:, 1].max()) > 0 and int(got[0][1][0]) > 1
+        cs = g.launch()["chunk_syms"]
+        assert sum((len(f) + cs - 1) // cs for f in files) > 256
+        q = gen.from_files([piece(50_000 * scale, 300_000 * scale) for _ in range(4)]
+                           + [rng.integers(0, 1 << bits, size=100_000, dtype=np.uint8), seq[:n - 1],
+                              np.zeros(0, np.uint8)], bits)
+        _check_all_featurize_forms(g, o, corpus, q, "%d-bit keys in place" % (n * bits))
     finally:
         g.close()
 
