@@ -1,8 +1,10 @@
 """Write expected pass tables for full-size workloads, computed by the CPU oracle only.
 
 Usage: python tests/golden/make_golden.py WORKLOAD [--threads T] [--m M] [--table-out FILE.npz]
+                                          [--freq doc|occ] [--nmax N]
 
-For each pass of the chain (n = 1..N, k_keep = K, Eq. 2 frequency) it stores
+For each pass of the chain (n = 1..N, k_keep = K, Eq. 2 frequency by default, Eq. 1 with
+--freq occ, which writes workload<W>_occ.json; --nmax cuts the chain short) it stores
 the kept length, the SHA-256 of the ordered table (little-endian uint64 triples
 key_lo, key_hi, count) and the first and last entries, plus the corpus digest,
 in tests/golden/workload<W>.json.  With --table-out, the last pass's whole ordered table (keys as
@@ -47,15 +49,20 @@ def main():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--out", default=None)
     ap.add_argument("--table-out", default=None, help="npz file for the last pass's ordered table")
+    ap.add_argument("--freq", choices=["doc", "occ"], default="doc")
+    ap.add_argument("--nmax", type=int, default=None)
     a = ap.parse_args()
     nmax, k_keep = CHAINS[a.workload]
+    nmax = min(nmax, a.nmax or nmax)
     corpus = gen.workload(a.workload, m=a.m, nthreads=a.threads)
     rec = {"workload": a.workload, "m": corpus.m, "symbol_bits": corpus.symbol_bits, "bytes": corpus.nbytes,
-           "corpus_sha256": corpus.sha256(), "freq": "doc", "k_keep": k_keep, "passes": {}}
-    o = oracle.Oracle(corpus.symbol_bits, oracle.FREQ_DOC, nthreads=a.threads)
+           "corpus_sha256": corpus.sha256(), "freq": a.freq, "k_keep": k_keep, "passes": {}}
+    o = oracle.Oracle(corpus.symbol_bits, oracle.FREQ_OCC if a.freq == "occ" else oracle.FREQ_DOC,
+                      nthreads=a.threads)
     o.load(corpus)
     out = a.out or os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                "workload%d%s.json" % (a.workload, "" if a.m is None else "_m%d" % a.m))
+                                "workload%d%s%s.json" % (a.workload, "" if a.m is None else "_m%d" % a.m,
+                                                         "_occ" if a.freq == "occ" else ""))
     for n in range(1, nmax + 1):
         t0 = time.time()
         rc = o.pass_(n, k_keep)

@@ -235,11 +235,101 @@ def _pass1_exact(buf, offs, keys, counts, k, what):
     assert [(int(keys[i, 0]), int(counts[i])) for i in range(len(counts))] == [(s, c) for c, s in present], what
 
 
+_CORPUS = {}
+
+
+def _workload(w):
+    """The full-size corpus of workload w, generated once for the tests that share it."""
+    if w not in _CORPUS:
+        _CORPUS.clear()
+        t0 = time.time()
+        _CORPUS[w] = gen.workload(w, nthreads=min(16, os.cpu_count() or 1))
+        say("workload %d full size: %d sequences, %d bytes (%.1fs)" % (w, _CORPUS[w].m, _CORPUS[w].nbytes,
+                                                                       time.time() - t0))
+    return _CORPUS[w]
+
+
+def _stream_pair_counts(buf):
+    """counts[a, b] = positions i of the byte stream with buf[i] = a and buf[i+1] = b (pairs that
+    straddle a sequence boundary included), from the stream read as little-endian 16-bit words
+    at even and then at odd offsets."""
+    from concurrent.futures import ThreadPoolExecutor
+    step = 1 << 24
+    parts = [np.frombuffer(buf, dtype="<u2", count=(len(buf) - off) // 2, offset=off) for off in (0, 1)]
+    spans = [(w, s) for w in parts for s in range(0, len(w), step)]
+    with ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        cnt = sum(ex.map(lambda t: np.bincount(t[0][t[1]:t[1] + step], minlength=1 << 16), spans),
+                  np.zeros(1 << 16, np.int64))
+    # the word at offset i is buf[i] | buf[i + 1] << 8
+    return cnt.reshape(256, 256).T
+
+
+def _occ_table(counts):
+    """(key, count) of every nonzero entry, in (count desc, key asc) order."""
+    keys = np.nonzero(counts)[0]
+    order = np.lexsort((keys, -counts[keys]))
+    return [(int(keys[i]), int(counts[keys[i]])) for i in order]
+
+
+def test_workload3_eq1_64bit_counters(golden_dir):
+    """Eq. 1 on the full text corpus: 2^32 windows at n = 1, so 32-bit counts are refused with
+    IG_EOVERFLOW and the 64-bit device counters are used.  Passes 1..3 (k_keep = 1e6, which keeps
+    every gram present) equal the oracle's tables by the digests make_golden.py --freq occ wrote,
+    and passes 1 and 2 equal exact occurrence counts of every byte and byte pair of the files."""
+    with open(os.path.join(golden_dir, "workload3_occ.json")) as fh:
+        gold = json.load(fh)
+    assert gold["freq"] == "occ"
+    corpus = _workload(3)
+    assert corpus.m == gold["m"] and corpus.nbytes == gold["bytes"] and corpus.sha256() == gold["corpus_sha256"]
+    k = gold["k_keep"]
+    assert corpus.nbytes >= 1 << 32
+    say("workload 3, Eq. 1: 32-bit counts refused with IG_EOVERFLOW")
+    g32 = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_OCC, count_bits=32)
+    try:
+        g32.load(corpus)
+        assert g32.try_pass(1, k) == ig.IG_EOVERFLOW
+        assert g32.table_info() == (0, 0)
+    finally:
+        g32.close()
+    say("workload 3, Eq. 1 with 64-bit counters: passes 1..%d" % len(gold["passes"]))
+    g = ig.Intergrams(symbol_bits=8, freq=ig.FREQ_OCC, count_bits=64)
+    tables = []
+    try:
+        g.load(corpus)
+        for n in range(1, len(gold["passes"]) + 1):
+            g.pass_(n, k)
+            keys, counts = g.topk()
+            tables.append((keys.copy(), counts.copy()))
+            exp = gold["passes"][str(n)]
+            assert len(counts) == exp["kept"], "pass %d: kept %d vs %d" % (n, len(counts), exp["kept"])
+            for i, (key, c) in enumerate(exp["head"]):
+                assert (_key_int(keys, i), int(counts[i])) == (int(key), c), (n, i)
+            assert table_digest(keys, counts) == exp["sha256"], "Eq. 1 pass %d digest" % n
+    finally:
+        g.close()
+    t0 = time.time()
+    buf = corpus.data
+    pairs = _stream_pair_counts(buf)
+    ones = pairs.sum(axis=1)
+    ones[int(buf[-1])] += 1
+    assert int(ones.sum()) == corpus.nbytes
+    offs = np.asarray(corpus.offsets, np.int64)
+    cut = np.unique(offs[(offs > 0) & (offs < corpus.nbytes)])
+    np.subtract.at(pairs, (buf[cut - 1], buf[cut]), 1)
+    assert int(pairs.sum()) == corpus.nbytes - len(cut) - 1
+    for n, exact in ((1, ones), (2, pairs.reshape(-1))):
+        keys, counts = tables[n - 1]
+        assert int(keys[:, 1].max()) == 0
+        got = [(int(keys[i, 0]), int(counts[i])) for i in range(len(counts))]
+        assert got == _occ_table(exact), "Eq. 1 pass %d vs exact occurrence counts" % n
+    assert int(tables[0][1][0]) < 1 << 32 <= int(tables[0][1].sum())
+    say("workload 3, Eq. 1: passes 1 and 2 equal exact byte and byte-pair counts (%.1fs)" % (time.time() - t0))
+
+
 @pytest.mark.parametrize("workload,nmax,k,sample_ns", [(3, 16, 1000000, [2, 16]), (4, 31, 1000000, [2, 31])])
 def test_full_size_properties_and_samples(golden_dir, workload, nmax, k, sample_ns):
     t0 = time.time()
-    corpus = gen.workload(workload, nthreads=min(16, os.cpu_count() or 1))
-    say("workload %d full size: %d sequences, %d bytes (%.1fs)" % (workload, corpus.m, corpus.nbytes, time.time() - t0))
+    corpus = _workload(workload)
     tables = _run_chain(corpus, nmax, k)
     say("workload %d: chain n=1..%d done (%.1fs)" % (workload, nmax, time.time() - t0))
     # the oracle's digests of every pass, where make_golden.py has written them
@@ -270,6 +360,7 @@ def test_full_size_properties_and_samples(golden_dir, workload, nmax, k, sample_
     say("workload %d: order and prefix closure hold on every pass (%.1fs)" % (workload, time.time() - t0))
     buf, offs = _symbols_as_bytes(corpus)
     del corpus
+    _CORPUS.clear()
     _pass1_exact(buf, offs, *tables[0], k, "pass 1")
     rng = np.random.default_rng(1000 + workload)
     _sampled_counts(buf, offs, tables, bits, sample_ns, rng, "workload %d" % workload)
