@@ -91,6 +91,18 @@ def test_workload3_sample_128bit_keys(m, k):
     assert_tables_equal(got, exp, "workload3 m=%d" % m)
 
 
+@pytest.mark.parametrize("m,k", [(300, 1000000), (400, 3000)])
+def test_workload3_occ_sample_128bit_keys(m, k):
+    """Eq. 1 over bytes with windows of more than 64 bits (n = 9..16), which the scan keeps in
+    place: every pass of the text sample equals the oracle's."""
+    corpus = gen.workload(3, m=m)
+    ns = list(range(1, 17))
+    say("workload 3 first %d docs, Eq. 1, n=1..16, k=%d" % (m, k))
+    exp, _ = oracle_tables(corpus, ns, k, occ=True)
+    got, _ = gpu_tables(corpus, ns, k, occ=True)
+    assert_tables_equal(got, exp, "workload3 occ m=%d" % m)
+
+
 @pytest.mark.parametrize("m,k", [(12, 1000000), (20, 5000)])
 def test_workload4_sample_2bit(m, k):
     corpus = gen.workload(4, m=m)
