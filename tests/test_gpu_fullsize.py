@@ -273,9 +273,10 @@ def _occ_table(counts):
 
 def test_workload3_eq1_64bit_counters(golden_dir):
     """Eq. 1 on the full text corpus: 2^32 windows at n = 1, so 32-bit counts are refused with
-    IG_EOVERFLOW and the 64-bit device counters are used.  Passes 1..3 (k_keep = 1e6, which keeps
-    every gram present) equal the oracle's tables by the digests make_golden.py --freq occ wrote,
-    and passes 1 and 2 equal exact occurrence counts of every byte and byte pair of the files."""
+    IG_EOVERFLOW and the 64-bit device counters are used.  Every pass of the stored chain (n =
+    1..12, k_keep = 1e6; from n = 9 on the windows take more than 64 bits) equals the oracle's
+    table by the digests make_golden.py --freq occ wrote, and passes 1 and 2 (which keep every
+    gram present) equal exact occurrence counts of every byte and byte pair of the files."""
     with open(os.path.join(golden_dir, "workload3_occ.json")) as fh:
         gold = json.load(fh)
     assert gold["freq"] == "occ"
