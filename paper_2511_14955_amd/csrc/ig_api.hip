@@ -452,6 +452,21 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   if (scan_lds_bytes(p, mode, occ) > lds_budget)
     return set_error(c, IG_EINVAL, "launch configuration needs %llu bytes of LDS",
                      (unsigned long long)scan_lds_bytes(p, mode, occ));
+  // A direct-indexed pass over at most sigma^n distinct grams, no more than a chunk has windows,
+  // repeats candidates within every full chunk; a set that cannot hold them twice over would fill
+  // and then count (Eq. 1) or record (Eq. 2) the rest of the chunk once per window.  Its set grows
+  // instead, up to twice sigma^n (at most 32768 entries), while the pass's LDS budget allows.
+  // (Over a larger space the chunks hold mostly distinct grams, and a larger set only costs.)
+  uint64_t grams = 1;   // sigma^n, capped
+  for (uint32_t j = 0; j < n && grams <= c->lc.chunk_syms; j++) grams *= c->sigma;
+  if (mode == MODE_DENSE && grams <= c->lc.chunk_syms)
+    while (p.set_cap < 2 * grams && p.set_cap < 32768u) {
+      p.set_cap <<= 1;
+      if (scan_lds_bytes(p, mode, occ) > lds_budget) {
+        p.set_cap >>= 1;
+        break;
+      }
+    }
   const uint32_t block = c->lc.block;
   const uint32_t grid = (uint32_t)c->n_cu * wpc;
   c->last.set_cap = p.set_cap;

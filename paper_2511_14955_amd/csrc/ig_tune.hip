@@ -146,7 +146,7 @@ extern "C" int ig_autotune(ig_ctx *c, uint32_t n, uint64_t k_keep, ig_tune_repor
       int rc = ig_pass(c, n, k_keep);
       if (rc == IG_EINVAL) return -1.0;   // launch shape does not fit this pass
       if (rc) return -2.0 + rc;
-      if (c->last.set_cap != lc.set_cap) {   // ran only with a smaller LDS set: unusable here
+      if (c->last.set_cap < lc.set_cap) {   // ran only with a smaller LDS set: unusable here
         rc = ig_rewind(c);
         return rc ? -2.0 + rc : -1.0;
       }

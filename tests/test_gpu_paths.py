@@ -10,6 +10,7 @@
 - A chunk with more distinct candidates than its LDS set holds (the set is bypassed for the
   rest of the chunk), and a pass run as the direct-indexed count inside a chain because the
   previous pass kept every (n-1)-gram of the alphabet.
+- Direct-indexed passes over at most a chunk's worth of grams grow their LDS set.
 """
 import time
 
@@ -253,5 +254,34 @@ def test_direct_count_with_part_of_the_prefixes_kept(bits, occ):
     got, g = gpu_tables(corpus, ns, k, occ)
     try:
         assert_tables_equal(got, exp, "part of the prefixes kept")
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("occ", [False, True])
+def test_direct_indexed_passes_grow_their_set(occ):
+    """Random 2-bit files with a 4096-entry LDS set: passes 6 and 7 count all 4^6 and 4^7 grams
+    directly (every shorter gram kept), no more than a chunk has windows, so their sets grow past
+    4096 entries; pass 8 (4^8 grams, more than a chunk's windows) keeps the launch's set.  Every
+    table equals the oracle's."""
+    rng = np.random.default_rng(6060 + occ)
+    files = [rng.integers(0, 4, size=int(rng.integers(200_000, 400_000)), dtype=np.uint8) for _ in range(6)]
+    corpus = gen.from_files(files, 2)
+    ns, k = list(range(1, 9)), 1_000_000
+    say("direct-indexed passes grow their set: 2-bit, n=1..8, launch set 4096, %s" % ("Eq. 1" if occ else "Eq. 2"))
+    exp, _ = oracle_tables(corpus, ns, k, occ)
+    g = ig.Intergrams(symbol_bits=2, freq=ig.FREQ_OCC if occ else ig.FREQ_DOC)
+    try:
+        g.set_launch(23552, 1024, 4096, 1)
+        g.load(corpus)
+        got, caps = [], []
+        for n in ns:
+            g.pass_(n, k)
+            keys, counts = g.topk()
+            got.append((keys.copy(), counts.copy()))
+            caps.append(g.last_stats()["set_cap"])
+        assert_tables_equal(got, exp, "growing sets")
+        assert caps[5] >= 8192 and caps[6] >= 16384 and caps[7] == 4096, caps
+        assert g.launch()["set_cap"] == 4096
     finally:
         g.close()
