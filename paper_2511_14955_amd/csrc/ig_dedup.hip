@@ -287,6 +287,16 @@ __global__ void __launch_bounds__(GATHER_BLOCK) k_gather(DedupParams d) {
   }
 }
 
+// The level-2 kernels take tiles strided by the grid.  Workgroups are dispatched to the 8 XCDs
+// round-robin by id, and neighbouring tiles share the cache lines of their per-digit counts and
+// bases (entry d2 * ntb + tl of a bucket): numbered as below, the workgroups of one XCD take
+// consecutive tiles, so those lines are filled and read within one L2.  (A bijection of
+// [0, grid) when the grid is a multiple of 8; the identity otherwise.)
+__device__ __forceinline__ uint32_t xcd_major_block() {
+  const uint32_t g = gridDim.x, b = blockIdx.x;
+  return g % 8u ? b : (b % 8u) * (g / 8u) + b / 8u;
+}
+
 // bucket of tile t: the last b with base1[b] <= t * TILE (empty buckets have no tiles)
 __device__ __forceinline__ uint32_t tile_bucket(const uint64_t *s_base1, uint32_t nb1, uint64_t pos) {
   uint32_t lo = 0, hi = nb1;   // invariant: base1[lo] <= pos < base1[hi]
@@ -315,7 +325,7 @@ __global__ void __launch_bounds__(P2_BLOCK) k_p2_hist(DedupParams d) {
   const uint64_t ntiles = d.dscal[1];
   const R1 *in = reinterpret_cast<const R1 *>(d.l1);
   const uint32_t dm = d.nb2 - 1;
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  for (uint64_t t = xcd_major_block(); t < ntiles; t += gridDim.x) {
     const uint64_t pos = t * TILE;
     const uint32_t b = tile_bucket(s_base1, d.nb1, pos);
     const uint64_t tb = s_base1[b] / TILE, ntb = (s_base1[b + 1] - s_base1[b]) / TILE, tl = t - tb;
@@ -393,8 +403,9 @@ __global__ void __launch_bounds__(P2_BLOCK) __attribute__((amdgpu_waves_per_eu(5
 #pragma unroll
     for (uint32_t q = 0; q < SLICE_ROUNDS; q++) rn[q] = in[i0 + q * 64];
   };
-  if (blockIdx.x < ntiles) load_tile(blockIdx.x);
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  const uint32_t vb = xcd_major_block();
+  if (vb < ntiles) load_tile(vb);
+  for (uint64_t t = vb; t < ntiles; t += gridDim.x) {
     for (uint32_t k = tid; k < NW * d.nb2; k += P2_BLOCK) wcur_[k] = 0;
     __syncthreads();
     const uint64_t pos = t * TILE;
