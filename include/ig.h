@@ -194,8 +194,8 @@ typedef struct {
   uint64_t records;      /* Eq. 2: chunk-distinct (candidate, sequence) records counted once per sequence */
   double   dedup_ms;     /* Eq. 2: counting the records once per sequence */
   uint32_t set_cap;      /* the scan's LDS set size in use: the launch's, halved while it did not
-                            fit this pass's LDS, or, for a direct-indexed pass over few grams,
-                            grown toward twice their number (results do not depend on it) */
+                            fit this pass's LDS, or, for a direct-indexed pass whose chunks
+                            repeat their grams, grown (results do not depend on it) */
   uint32_t reserved;
 } ig_pass_stats;
 int  ig_last_pass_stats(const ig_ctx *ctx, ig_pass_stats *st);
@@ -224,8 +224,10 @@ const char *ig_last_error(const ig_ctx *ctx);
  * halves the set further until it fits (down to block entries).  A directly
  * indexed pass (every n-gram of the alphabet a candidate) over at most
  * chunk_syms grams (sigma^n over the corpus's alphabet) grows a set smaller
- * than twice that, up to twice it or 32768 entries, while its LDS allows.
- * ig_last_pass_stats reports the set size the pass ran with.
+ * than twice that, up to twice it or 32768 entries, while its LDS allows; so
+ * does an Eq. 2 one over more grams whose previous table's pass made at most
+ * one record per 8 windows.  ig_last_pass_stats reports the set size the pass
+ * ran with.
  *
  * ig_autotune runs pass n on the loaded corpus for each candidate shape
  * (rewinding after each), checks that all candidates return the same table,

@@ -455,11 +455,16 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   // A direct-indexed pass over at most sigma^n distinct grams, no more than a chunk has windows,
   // repeats candidates within every full chunk; a set that cannot hold them twice over would fill
   // and then count (Eq. 1) or record (Eq. 2) the rest of the chunk once per window.  Its set grows
-  // instead, up to twice sigma^n (at most 32768 entries), while the pass's LDS budget allows.
-  // (Over a larger space the chunks hold mostly distinct grams, and a larger set only costs.)
+  // instead, up to twice sigma^n (at most 32768 entries), while the pass's LDS budget allows.  So
+  // does an Eq. 2 pass over more grams when the pass that made the previous table recorded at
+  // most one candidate per 8 windows: its chunks then repeated their (n-1)-grams, and their
+  // n-grams likely repeat too.  (Over a larger space whose chunks hold mostly distinct grams, a
+  // larger set only costs.)
   uint64_t grams = 1;   // sigma^n, capped
   for (uint32_t j = 0; j < n && grams <= c->lc.chunk_syms; j++) grams *= c->sigma;
-  if (mode == MODE_DENSE && grams <= c->lc.chunk_syms)
+  const bool repeats_prev = !occ && filtered && c->T().made_windows > 0 &&
+                            c->T().made_records * 8 <= c->T().made_windows;
+  if (mode == MODE_DENSE && (grams <= c->lc.chunk_syms || repeats_prev))
     while (p.set_cap < 2 * grams && p.set_cap < 32768u) {
       p.set_cap <<= 1;
       if (scan_lds_bytes(p, mode, occ) > lds_budget) {
@@ -723,6 +728,8 @@ int ig_pass(ig_ctx *c, uint32_t n, uint64_t k_keep) {
   TableSet &nt = c->ts[c->nxt];
   nt.kept = kept;
   nt.n = n;
+  nt.made_windows = W;
+  nt.made_records = occ ? 0 : c->last.records;
   {
     const int old_prev = c->prev;
     c->prev = c->cur;

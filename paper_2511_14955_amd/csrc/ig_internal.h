@@ -371,6 +371,8 @@ struct TableSet {
   uint32_t n = 0, filt_words = 0, filt_kind = 0;
   bool has_qmap = false, has_qmap2 = false;
   QMapShape qs{}, qs2{};
+  // the pass that made the table: its windows and (Eq. 2) chunk-distinct records
+  uint64_t made_windows = 0, made_records = 0;
 };
 
 struct LaunchCfg {
