@@ -203,7 +203,8 @@ def test_occ_64bit_counters_and_eoverflow():
 @pytest.mark.parametrize("occ", [False, True])
 def test_set_overflow_bypass_and_dense_chain_pass(occ):
     """Random bytes: pass 1 keeps all 256 symbols, so pass 2 is the direct-indexed count of all
-    2-grams inside the chain; pass 3 (k = 60,000 prefixes) has far more distinct candidates per
+    2-grams inside the chain (under Eq. 2 with a grown LDS set, pass 1 having made few records per
+    window); pass 3 (k = 60,000 prefixes) has far more distinct candidates per
     chunk than the chunk's LDS set holds, so its chunks fill the set and bypass it (straight to
     the counters for Eq. 1, to records for Eq. 2).  Every table equals the oracle's."""
     rng = np.random.default_rng(2027 + occ)
@@ -224,6 +225,10 @@ def test_set_overflow_bypass_and_dense_chain_pass(occ):
             st = g.last_stats()
             if n == 1:
                 assert g.table_info()[1] == 256
+            if n == 2:
+                # 65,536 grams, more than a chunk has windows; under Eq. 2 the set still grows,
+                # since pass 1 recorded at most one candidate per 8 windows
+                assert (st["set_cap"] > lc["set_cap"]) == (not occ), (st["set_cap"], lc)
             if n == 3 and not occ:
                 # more records than the sets of all chunks could hold: the set was bypassed
                 nchunks = sum((len(f) + lc["chunk_syms"] - 1) // lc["chunk_syms"] for f in files)
